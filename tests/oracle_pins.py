@@ -1,0 +1,165 @@
+"""Pins for the CPU oracle: checks against facts that the paper or plain
+mathematics fix, written so that a plausible slip anywhere in the oracle
+(a dropped term, a wrong sign, a transposed operand) changes at least one of
+the returned error measures.  Each function returns an error (0 when exact);
+tests compare it against a threshold and the mutation tests check that planted
+mistakes push it over.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import mfipm_ref as R
+
+
+def rng_for(seed):
+    return np.random.default_rng(np.random.PCG64(seed))
+
+
+def dense_problem(m, n, k, seed, sigma=1e-3, c_tau=1e-2):
+    rng = rng_for(seed)
+    A = rng.standard_normal((m, n)) / math.sqrt(m)
+    x = np.zeros(n)
+    S = rng.choice(n, k, replace=False)
+    x[S] = rng.standard_normal(k)
+    b = A @ x + sigma * rng.standard_normal(m)
+    tau = c_tau * float(np.max(np.abs(A.T @ b)))
+    return A, b, tau, x
+
+
+def pin_zero_solution(op, b, scale=1.5):
+    """tau >= ||A^T b||_inf makes x = 0 optimal (0 is in the subdifferential).
+    Returns ||x||_inf / (1 + ||b||_inf)."""
+    tau = scale * float(np.max(np.abs(op.rmatvec(b))))
+    res = R.solve(op, b, tau)
+    assert res.status == R.CONVERGED, res.status
+    return float(np.max(np.abs(res.x))) / (1.0 + float(np.max(np.abs(b))))
+
+
+def pin_orthonormal_soft_threshold(op, b, tau):
+    """A^T A = I  =>  x* = soft(A^T b, tau).  Returns the relative error."""
+    res = R.solve(op, b, tau, R.Params(tol=1e-12))
+    ref = R.soft_threshold(op.rmatvec(b), tau)
+    return float(np.linalg.norm(res.x - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def pin_brute_force(A, b, tau):
+    """Relative distance of the oracle solution from the enumerated minimiser."""
+    xb, _ = R.brute_force_bpdn(A, b, tau)
+    res = R.solve(R.DenseOperator(A), b, tau, R.Params(tol=1e-12))
+    return float(np.linalg.norm(res.x - xb) / max(np.linalg.norm(xb), 1e-300))
+
+
+def pin_kkt(op, b, tau, params=None):
+    """KKT residual of the oracle solution (|g_i| <= tau, g_S = -tau sign x_S)."""
+    res = R.solve(op, b, tau, params)
+    S, sg = R.support_from_state(res.z, res.s, op.n)
+    return R.kkt_residual(op, b, tau, res.x, S, sg), res
+
+
+def pin_newton_blocks(op, seed):
+    """H-apply and P^{-1} against their dense block definitions, and
+    Theorem (thm:ne2_prec): P^{-1} H has eigenvalue 1 with multiplicity n, the
+    other n eigenvalues are those of the n x n pair with Theta_u + Theta_v.
+    Returns the largest of the discrepancies."""
+    n = op.n
+    rng = rng_for(seed)
+    theta_inv = 10.0 ** rng.uniform(-4, 4, 2 * n)
+    rho = op.frob2() / n
+    H = R.dense_newton_matrix(op, theta_inv)
+    P = R.dense_preconditioner(theta_inv, rho)
+    p = rng.standard_normal(2 * n)
+    e1 = np.linalg.norm(R.newton_apply(op, theta_inv, p) - H @ p) / np.linalg.norm(H @ p)
+    e2 = np.linalg.norm(R.precond_solve(theta_inv, rho, p) - np.linalg.solve(P, p)) / \
+        np.linalg.norm(np.linalg.solve(P, p))
+    # the explicit H itself against the product definition Theta^{-1} + F F^T
+    A = op.dense()
+    F = np.vstack([A.T, -A.T])  # F = [A^T; -A^T] so that F^T = [A, -A]
+    e0 = np.linalg.norm(H - (np.diag(theta_inv) + F @ F.T)) / np.linalg.norm(H)
+    # spectrum: generalized symmetric problem H v = lambda P v
+    import scipy.linalg
+    lam = np.sort(scipy.linalg.eigh(H, P, eigvals_only=True))
+    ones = np.abs(lam - 1.0) < 1e-8 * max(1.0, float(np.max(np.abs(lam))))
+    e3 = abs(int(np.sum(ones)) - n)  # exactly n unit eigenvalues
+    th = 1.0 / theta_inv
+    tbar_inv = 1.0 / (th[:n] + th[n:])
+    Hn = A.T @ A + np.diag(tbar_inv)
+    Pn = np.diag(tbar_inv + rho)
+    lam_n = np.sort(scipy.linalg.eigh(Hn, Pn, eigvals_only=True))
+    rest = np.sort(np.concatenate([lam[~ones], np.ones(int(np.sum(ones)) - n)])) \
+        if np.sum(ones) >= n else lam
+    lam_all = np.sort(np.concatenate([np.ones(n), lam_n]))
+    e4 = float(np.max(np.abs(lam_all - lam)) / max(1.0, float(np.max(lam))))
+    del rest
+    return max(e0, e1, e2, float(e3), e4)
+
+
+def pin_dct_definition(n, m, seed):
+    """Partial DCT against the cosine-sum definition and A A^T = I_m."""
+    rng = rng_for(seed)
+    rows = np.sort(rng.choice(n, m, replace=False))
+    op = R.PartialDCTOperator(n, rows)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    # cosine sum written out directly (independent of op.dense())
+    j = np.arange(n)
+    ref = np.array([(math.sqrt(1.0 / n) if k == 0 else math.sqrt(2.0 / n)) *
+                    np.sum(x * np.cos(math.pi * (2 * j + 1) * k / (2 * n))) for k in rows])
+    e1 = np.linalg.norm(op.matvec(x) - ref) / np.linalg.norm(ref)
+    # adjoint identity <A x, y> = <x, A^T y>
+    e2 = abs(op.matvec(x) @ y - x @ op.rmatvec(y)) / (np.linalg.norm(x) * np.linalg.norm(y))
+    # orthonormal rows
+    e3 = np.linalg.norm(op.matvec(op.rmatvec(y)) - y) / np.linalg.norm(y)
+    return max(e1, e2, e3)
+
+
+def pin_pcg_vs_direct(A, b, tau):
+    """With PCG run to 1e-12 the IPM takes the same iterations and reaches the
+    same point as with exact (Cholesky) Newton directions (Section 7.6:
+    PCG needs as few IPM iterations as the direct solver).  Returns
+    (|iteration difference|, relative x difference)."""
+    op = R.DenseOperator(A)
+    p_it = R.Params(tolpcg=1e-12, mxiterpcg=10 * A.shape[1])
+    r1 = R.solve(op, b, tau, p_it)
+    r2 = R.solve(op, b, tau, p_it, linsolve="direct")
+    return abs(r1.ipm_iters - r2.ipm_iters), float(np.linalg.norm(r1.x - r2.x) / np.linalg.norm(r2.x))
+
+
+def pin_duality(A, b, tau):
+    """At the exact minimiser the gap certificate is zero (strong duality), and
+    it is non-negative at any z (weak duality).  Returns max(|gap at x*|,
+    largest negative gap over random z)."""
+    op = R.DenseOperator(A)
+    xb, _ = R.brute_force_bpdn(A, b, tau)
+    z = np.concatenate([np.maximum(xb, 0), np.maximum(-xb, 0)])
+    _, r, g, primal = R.objective_terms(op, b, tau, z)
+    gap0, _ = R.relative_gap(b, tau, r, g, primal)
+    worst = 0.0
+    rng = rng_for(7)
+    for _ in range(20):
+        zz = np.abs(rng.standard_normal(2 * A.shape[1]))
+        _, r, g, primal = R.objective_terms(op, b, tau, zz)
+        gp, _ = R.relative_gap(b, tau, r, g, primal)
+        worst = max(worst, -gp)
+    # the primal value equals the BPDN objective of x = u - v when u, v have
+    # disjoint supports
+    fb = R.bpdn_objective(op, b, tau, xb)
+    _, _, _, pz = R.objective_terms(op, b, tau, z)
+    return max(abs(gap0), worst, abs(fb - pz) / (1 + abs(fb)))
+
+
+def pin_gradient(A, b, tau, x_true):
+    """Adjoint gradient at a tightly converged solve against the closed form
+    on the support.  Returns the largest relative error over dL/db, dL/dtau."""
+    op = R.DenseOperator(A)
+    prm = R.Params(tol=1e-13, tolpcg=1e-10, mxiterpcg=2000)
+    res = R.solve(op, b, tau, prm)
+    S, sg = R.support_from_state(res.z, res.s, op.n)
+    gx = res.x - x_true
+    gb_cf, gt_cf = R.closed_form_gradient(A[:, S], sg, res.x[S], x_true[S])
+    gr = R.backward(op, res.z, res.s, gx, prm)
+    eb = np.linalg.norm(gr.grad_b - gb_cf) / np.linalg.norm(gb_cf)
+    et = abs(gr.grad_tau - gt_cf) / abs(gt_cf)
+    return max(eb, et)

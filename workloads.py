@@ -1,0 +1,174 @@
+"""Seeded synthetic inputs for the l1-regularised least-squares solver.
+
+This module only *draws* problem instances: measurement operators (a dense
+Gaussian matrix or a set of sampled DCT rows), sparse signals, noise, the
+observations b and the regularisation weight tau.  It contains none of the
+solver's arithmetic and is shared, as input, by the CPU oracle tests and by
+the GPU harness (tests, bench).
+
+Problem family (paper, Section 1, eqs. (incomplsysnoisy) and
+(formulationsnoisy1)): b = A x_true + e with e_i ~ N(0, sigma^2), and
+tau = c_tau * ||A^T b||_inf.
+
+Operators:
+  * dense: A with i.i.d. N(0, 1/m) entries, row-major (C order), m x n;
+  * partial DCT: A = R_m C, where C is the orthonormal DCT-II of length n and
+    R_m keeps m distinct rows drawn uniformly without replacement, sorted
+    ascending (paper, Section 3 orthonormal rows, eq. (eq:orthonormality), and
+    Section 6 phase-transition setup "normalized DCT").
+
+Draw order inside one instance is fixed: operator (A or rows) -> support ->
+amplitudes / signs -> noise.  Every generator is numpy's PCG64 with the stated
+seed.  The observation b is formed on the host in FP64 (matmul or
+scipy.fft.dct); tau from A^T b likewise.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.fft
+
+__all__ = [
+    "DenseInstance", "DCTInstance", "dense_instance", "dct_instance",
+    "config_dense_256x1024", "config_pdct", "config_pdct_hdr",
+    "batched_dense_sizes", "batched_dense_instance", "config_dct_batch",
+    "dct_apply", "dct_apply_t",
+]
+
+
+def dct_apply(rows: np.ndarray, n: int, x: np.ndarray) -> np.ndarray:
+    """Rows `rows` of the orthonormal DCT-II of x (input synthesis only)."""
+    return scipy.fft.dct(np.asarray(x, np.float64), type=2, norm="ortho")[rows]
+
+
+def dct_apply_t(rows: np.ndarray, n: int, y: np.ndarray) -> np.ndarray:
+    """Transpose of dct_apply: zero-fill to length n, orthonormal DCT-III."""
+    full = np.zeros(n, np.float64)
+    full[rows] = y
+    return scipy.fft.idct(full, type=2, norm="ortho")
+
+
+def _sparse_signal(rng: np.random.Generator, n: int, k: int, amp: str) -> np.ndarray:
+    x = np.zeros(n, np.float64)
+    supp = rng.choice(n, size=k, replace=False)
+    if amp == "pm1":
+        x[supp] = rng.choice(np.array([-1.0, 1.0]), size=k)
+    elif amp == "normal":
+        x[supp] = rng.standard_normal(k)
+    elif amp == "hdr":  # +-10^(3U), U ~ U(0,1), random sign
+        mag = 10.0 ** (3.0 * rng.random(k))
+        sgn = rng.choice(np.array([-1.0, 1.0]), size=k)
+        x[supp] = sgn * mag
+    else:
+        raise ValueError(amp)
+    return x
+
+
+@dataclass
+class DenseInstance:
+    A: np.ndarray          # (m, n) float64, C order
+    b: np.ndarray          # (m,)
+    tau: float
+    x_true: np.ndarray     # (n,)
+    seed: int
+    label: str = ""
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+
+@dataclass
+class DCTInstance:
+    n: int
+    rows: np.ndarray       # (m,) int32, sorted, distinct
+    b: np.ndarray          # (m,) or (B, m)
+    tau: np.ndarray | float
+    x_true: np.ndarray     # (n,) or (B, n)
+    seed: int
+    label: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.rows.shape[0])
+
+
+def dense_instance(m: int, n: int, k: int, seed: int, amp: str = "normal",
+                   sigma: float = 1e-3, c_tau: float = 1e-2, label: str = "") -> DenseInstance:
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    x = _sparse_signal(rng, n, k, amp)
+    e = sigma * rng.standard_normal(m)
+    b = A @ x + e
+    tau = float(c_tau * np.max(np.abs(A.T @ b)))
+    return DenseInstance(A=np.ascontiguousarray(A), b=b, tau=tau, x_true=x, seed=seed, label=label)
+
+
+def dct_instance(n: int, m: int, k: int, seed: int, amp: str = "normal",
+                 sigma: float = 1e-2, c_tau: float = 1e-2, label: str = "") -> DCTInstance:
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    rows = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+    x = _sparse_signal(rng, n, k, amp)
+    e = sigma * rng.standard_normal(m)
+    b = dct_apply(rows, n, x) + e
+    tau = float(c_tau * np.max(np.abs(dct_apply_t(rows, n, b))))
+    return DCTInstance(n=n, rows=rows, b=b, tau=tau, x_true=x, seed=seed, label=label)
+
+
+# --- the five named workloads -------------------------------------------------
+
+def config_dense_256x1024() -> DenseInstance:
+    """Dense 256x1024 N(0,1/256), 20-sparse +-1 spikes, noise 1e-3, c_tau 1e-2."""
+    return dense_instance(256, 1024, 20, seed=120801, amp="pm1", sigma=1e-3, c_tau=1e-2,
+                          label="dense_256x1024")
+
+
+def config_pdct(n: int = 1 << 16) -> DCTInstance:
+    """Partial DCT n=2^16, m=n/4, k=floor(n/100) N(0,1), noise 1e-2, c_tau 1e-2."""
+    return dct_instance(n, n // 4, n // 100, seed=120802, amp="normal", sigma=1e-2, c_tau=1e-2,
+                        label=f"pdct_n{n}")
+
+
+def config_pdct_hdr(n: int = 1 << 20) -> DCTInstance:
+    """Partial DCT n=2^20, m=n/4, k=floor(n/200) +-10^U(0,3), noise 1e-3, c_tau 1e-3."""
+    return dct_instance(n, n // 4, n // 200, seed=120803, amp="hdr", sigma=1e-3, c_tau=1e-3,
+                        label=f"pdct_hdr_n{n}")
+
+
+def batched_dense_sizes(batch: int = 256, seed: int = 120804) -> np.ndarray:
+    """Signal lengths n_i = 64 * U{16..128} of the batched dense workload."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    return 64 * rng.integers(16, 129, size=batch)
+
+
+def batched_dense_instance(i: int, n: int, seed: int = 120804) -> DenseInstance:
+    """Instance i of the batched dense workload: m=n/4, k=floor(n/50) N(0,1)."""
+    return dense_instance(n // 4, n, n // 50, seed=seed * 1000 + i, amp="normal",
+                          sigma=1e-3, c_tau=1e-2, label=f"batched_dense_{i}")
+
+
+def config_dct_batch(n: int = 1 << 18, batch: int = 32, seed: int = 120805,
+                     sigma: float = 1e-2, c_tau: float = 5e-3) -> DCTInstance:
+    """`batch` signals sharing one partial DCT (m=n/4), k=floor(n/100) N(0,1)."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    m, k = n // 4, n // 100
+    rows = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+    X = np.zeros((batch, n))
+    Bm = np.zeros((batch, m))
+    taus = np.zeros(batch)
+    for j in range(batch):
+        X[j] = _sparse_signal(rng, n, k, "normal")
+        e = sigma * rng.standard_normal(m)
+        Bm[j] = dct_apply(rows, n, X[j]) + e
+        taus[j] = c_tau * np.max(np.abs(dct_apply_t(rows, n, Bm[j])))
+    drng = np.random.default_rng(np.random.PCG64(seed + 1))
+    direction = drng.standard_normal((batch, m))
+    direction /= np.linalg.norm(direction, axis=1, keepdims=True)
+    return DCTInstance(n=n, rows=rows, b=Bm, tau=taus, x_true=X, seed=seed,
+                       label=f"pdct_batch{batch}_n{n}", extra={"fd_direction": direction})
