@@ -1,0 +1,196 @@
+// Shared device-side building blocks of the mfIPM kernels (gfx950, wave64).
+// Workgroups are 512 threads (8 waves); reduction scratch in LDS holds
+// MF_RED_DOUBLES doubles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MF_THREADS 512
+#define MF_WAVES (MF_THREADS / 64)
+#define MF_MAXK 4  // partial-sum slots per pass
+#define MF_RED_DOUBLES (MF_WAVES * MF_MAXK + MF_MAXK)
+
+// Status / flag values shared with the host driver.
+enum {
+  ST_CONVERGED = 0,
+  ST_MAXITER = 1,
+  ST_PCG_BREAKDOWN = 2,
+  ST_NONFINITE = 3,
+  ST_STEP_UNDERFLOW = 4,
+  ST_ABORTED = 5,
+  ST_DEVICE_CHECK = 6,
+};
+
+struct cplx {
+  double x, y;
+};
+
+__device__ __forceinline__ cplx mkc(double a, double b) { return cplx{a, b}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx cconj(cplx a) { return cplx{a.x, -a.y}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.x * s, a.y * s}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by sign*i (sign = +1 or -1)
+__device__ __forceinline__ cplx cmul_si(cplx a, int sign) {
+  return sign > 0 ? cplx{-a.y, a.x} : cplx{a.y, -a.x};
+}
+
+// Roots of unity T(e) = exp(-2 pi i e / M) from two tables:
+// T(e) = hi[e >> lo_bits] * lo[e & (2^lo_bits - 1)].  Tables are built on the
+// host in extended precision.  `scale` maps an instance's own resolution
+// (4 n) onto the table resolution (4 n_max).
+struct Twiddle {
+  const cplx* __restrict__ lo;
+  const cplx* __restrict__ hi;
+  int lo_bits;
+  int scale_shift;
+  __device__ __forceinline__ cplx get(long e) const {
+    e <<= scale_shift;
+    cplx a = hi[e >> lo_bits];
+    cplx b = lo[e & ((1L << lo_bits) - 1)];
+    return cmul(a, b);
+  }
+  // exp(sign * 2 pi i e / M)
+  __device__ __forceinline__ cplx get(long e, int sign) const {
+    cplx t = get(e);
+    return sign < 0 ? t : cconj(t);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Teams: groups of workgroups that cooperate on one instance.  A team barrier
+// is a monotonically increasing counter; every workgroup of the team passes
+// the same sequence of barriers because all control decisions are taken from
+// identical, deterministically reduced values.  The wait is bounded in wall
+// clock time: past the bound a global abort flag is raised, later barriers
+// return at once and the solver loops stop, so the grid always drains.
+// ---------------------------------------------------------------------------
+struct Team {
+  int id;
+  int rank;
+  int size;
+  unsigned long long* bar;
+  unsigned long long gen;
+  int* abort_flag;
+  unsigned long long spin_ticks;  // bound on one wait, in wall-clock ticks
+};
+
+__device__ __forceinline__ int ld_flag(int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns nonzero if the run was aborted.
+__device__ inline int team_barrier(Team& t) {
+  __shared__ int s_abort;
+  __syncthreads();
+  t.gen += 1;
+  if (threadIdx.x == 0) {
+    int ab = ld_flag(t.abort_flag);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(t.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!ab) {
+      const unsigned long long target = t.gen * (unsigned long long)t.size;
+      const unsigned long long t0 = wall_clock64();
+      unsigned iter = 0;
+      while (__hip_atomic_load(t.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++iter & 255u) == 0) {
+          if (ld_flag(t.abort_flag)) {
+            ab = 1;
+            break;
+          }
+          if (wall_clock64() - t0 > t.spin_ticks) {
+            __hip_atomic_store(t.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ab = 1;
+            break;
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_abort = ab;
+  }
+  __syncthreads();
+  return s_abort;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions.  kind: 0 = sum, 1 = max, 2 = min.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rop(int kind, double a, double b) {
+  if (kind == 0) return a + b;
+  if (kind == 1) return fmax(a, b);
+  return fmin(a, b);
+}
+__device__ __forceinline__ double rid(int kind) {
+  return kind == 0 ? 0.0 : (kind == 1 ? -__builtin_inf() : __builtin_inf());
+}
+
+__device__ __forceinline__ double wave_reduce(int kind, double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = rop(kind, v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Reduce K per-thread values over the workgroup; thread 0 gets the results in
+// out[] (registers of thread 0).  All threads must call.
+template <int K>
+__device__ inline void wg_reduce(const int* kinds, double (&v)[K], double* lds_scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = wave_reduce(kinds[j], v[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) lds_scratch[wave * MF_MAXK + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double a = lds_scratch[j];
+      for (int w = 1; w < MF_WAVES; ++w) a = rop(kinds[j], a, lds_scratch[w * MF_MAXK + j]);
+      v[j] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Reduce per-item partials part[item * MF_MAXK + j] over items [0, nitems) in
+// a fixed order; every thread of the workgroup receives the K results.
+template <int K>
+__device__ inline void reduce_items(const int* kinds, const double* part, int nitems, double (&res)[K],
+                                    double* lds_scratch) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double a[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] = rid(kinds[j]);
+    for (int it = lane; it < nitems; it += 64) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) a[j] = rop(kinds[j], a[j], part[(long)it * MF_MAXK + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] = wave_reduce(kinds[j], a[j]);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) lds_scratch[MF_WAVES * MF_MAXK + j] = a[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < K; ++j) res[j] = lds_scratch[MF_WAVES * MF_MAXK + j];
+  __syncthreads();
+}
+
+// The 2x2 block preconditioner of the reduced Newton system,
+// P_i = [[tu + rho, -rho], [-rho, tv + rho]] (tu, tv = Theta^{-1} entries);
+// returns P_i^{-1} r.
+__device__ __forceinline__ void precond_apply(double tu, double tv, double rho, double ru, double rv,
+                                              double& yu, double& yv) {
+  const double det = tu * tv + rho * (tu + tv);
+  yu = ((tv + rho) * ru + rho * rv) / det;
+  yv = (rho * ru + (tu + rho) * rv) / det;
+}

@@ -1,0 +1,989 @@
+// Device-side driver of the single-corrector primal-dual matrix-free IPM
+// (Section 7.1 algorithm) and of its PCG inner solver (Section 5), written
+// once over an operator policy (OpDense / OpPdct).  Per-index data are
+// interleaved (u_i, v_i) pairs (double2) so that the 2x2 block structure of
+// H and P (Section 5, eqs. (eq:ne2_H), (eq:ne2_P)) is local to one index.
+//
+// Every pass distributes its items over the workgroups of a team; every
+// reduction is first done per item (fixed order inside the workgroup), then
+// over items in a fixed order by each workgroup after the team barrier, so
+// all workgroups of a team hold bit-identical scalars and take identical
+// branch decisions.
+#pragma once
+#include "common.h"
+#include "op_dense.h"
+#include "op_pdct.h"
+
+// mirror of mfipm_params (host struct) -- same field order and types
+struct DevParams {
+  double tol;
+  int32_t maxiters;
+  double tolpcg;
+  int32_t mxiterpcg;
+  double sigma1, sigma2, sigma3;
+  double alpha_bar, alpha_tilde;
+  double eta;
+  double rho;
+  double z0, s0;
+  double tolpcg_adj;
+  int32_t mxiterpcg_adj;
+  double step_min;
+};
+
+struct DevInfo {
+  int32_t status, ipm_iters, pcg_iters, correctors;
+  int64_t nmat;
+  double rel_gap, mu, primal_obj, dual_obj, rho;
+};
+
+struct InstDesc {
+  long n, m;
+  long n_off, m_off, a_off;
+  double tau;
+};
+
+// per-team workspace (device pointers)
+struct TeamWS {
+  double2 *X, *R, *P, *TI, *DZ, *DS, *Zs, *Ss;
+  double *D, *Yv;
+  cplx *Y1, *Y2;
+  unsigned char* mask;
+  double *bt, *XS;
+  double *partA, *partB, *partC, *partS;
+  unsigned long long* bar;
+  int* slot;
+  int* err;
+};
+
+struct TeamLayout {  // byte offsets inside one team region
+  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, Y1, Y2, mask, bt, XS, partA, partB, partC, partS, ctl;
+  long stride;
+};
+
+struct KArgs {
+  const InstDesc* inst;
+  const int* order;
+  int batch;
+  int* queue_head;
+  int* abort_flag;
+  DevInfo* info;
+  const double* A;
+  const int* rows;
+  int shared_op;
+  const double* b;
+  double* x;
+  double* state;
+  const double* grad_x;
+  double* grad_b;
+  double* grad_tau;
+  DevParams prm;
+  char* team_base;
+  TeamLayout lay;
+  const cplx* tw_lo;
+  const cplx* tw_hi;
+  int tw_lo_bits;
+  int tw_log2n_max;
+  int team_size;
+  int tile_param;
+  unsigned long long spin_ticks;
+};
+
+__device__ inline TeamWS make_ws(const KArgs& a, int team) {
+  char* base = a.team_base + (long)team * a.lay.stride;
+  TeamWS w;
+  w.X = (double2*)(base + a.lay.X);
+  w.R = (double2*)(base + a.lay.R);
+  w.P = (double2*)(base + a.lay.P);
+  w.TI = (double2*)(base + a.lay.TI);
+  w.DZ = (double2*)(base + a.lay.DZ);
+  w.DS = (double2*)(base + a.lay.DS);
+  w.Zs = (double2*)(base + a.lay.Zs);
+  w.Ss = (double2*)(base + a.lay.Ss);
+  w.D = (double*)(base + a.lay.D);
+  w.Yv = (double*)(base + a.lay.Yv);
+  w.Y1 = (cplx*)(base + a.lay.Y1);
+  w.Y2 = (cplx*)(base + a.lay.Y2);
+  w.mask = (unsigned char*)(base + a.lay.mask);
+  w.bt = (double*)(base + a.lay.bt);
+  w.XS = (double*)(base + a.lay.XS);
+  w.partA = (double*)(base + a.lay.partA);
+  w.partB = (double*)(base + a.lay.partB);
+  w.partC = (double*)(base + a.lay.partC);
+  w.partS = (double*)(base + a.lay.partS);
+  w.bar = (unsigned long long*)(base + a.lay.ctl);
+  w.slot = (int*)(base + a.lay.ctl + 64);
+  w.err = (int*)(base + a.lay.ctl + 128);
+  return w;
+}
+
+// ------------------------------------------------------------------------
+// Per-index functors.  load() issues the global reads of one index into
+// registers; gather()/scatter()/elem() compute, store, accumulate partials.
+// ------------------------------------------------------------------------
+
+// PCG pass A: y = P^{-1} r, p = y + beta p, d = p_u - p_v; acc0 += p^T Theta^{-1} p
+struct FPcgA {
+  static constexpr int K = 1;
+  struct In {
+    double2 r, ti, p;
+  };
+  double2* R;
+  double2* TI;
+  double2* P;
+  double beta, rho;
+  int first;
+  double acc[K];
+  __device__ void reset() { acc[0] = 0.0; }
+  __device__ void load(long i, In& in) const {
+    in.r = R[i];
+    in.ti = TI[i];
+    if (!first) in.p = P[i];
+  }
+  __device__ double gather(long i, const In& in) {
+    double yu, yv;
+    precond_apply(in.ti.x, in.ti.y, rho, in.r.x, in.r.y, yu, yv);
+    double2 p;
+    if (first) p = make_double2(yu, yv);
+    else p = make_double2(yu + beta * in.p.x, yv + beta * in.p.y);
+    P[i] = p;
+    acc[0] += in.ti.x * p.x * p.x + in.ti.y * p.y * p.y;
+    return p.x - p.y;
+  }
+};
+
+// PCG pass C: q = Theta^{-1} p + [t; -t]; x += alpha p; r -= alpha q;
+// acc0 += r^T P^{-1} r, acc1 += r^T r (new r)
+struct FPcgC {
+  static constexpr int K = 2;
+  struct In {
+    double2 p, ti, x, r;
+  };
+  double2* P;
+  double2* TI;
+  double2* X;
+  double2* R;
+  double alpha, rho;
+  double acc[K];
+  __device__ void reset() { acc[0] = acc[1] = 0.0; }
+  __device__ void load(long i, In& in) const {
+    in.p = P[i];
+    in.ti = TI[i];
+    in.x = X[i];
+    in.r = R[i];
+  }
+  __device__ void scatter(long i, double t, const In& in) {
+    const double qu = in.ti.x * in.p.x + t, qv = in.ti.y * in.p.y - t;
+    const double2 x = make_double2(in.x.x + alpha * in.p.x, in.x.y + alpha * in.p.y);
+    const double2 r = make_double2(in.r.x - alpha * qu, in.r.y - alpha * qv);
+    X[i] = x;
+    R[i] = r;
+    double yu, yv;
+    precond_apply(in.ti.x, in.ti.y, rho, r.x, r.y, yu, yv);
+    acc[0] += r.x * yu + r.y * yv;
+    acc[1] += r.x * r.x + r.y * r.y;
+  }
+};
+
+// Residual pass A: bring (z, s) up to date (initial point, pending step) or
+// form the trial point of the corrector; d = x = u - v.
+// acc0 += 1^T z, acc1 += z^T s.
+enum { RA_INIT = 0, RA_STEP = 1, RA_TRIAL = 2, RA_NONE = 3 };
+struct FResA {
+  static constexpr int K = 2;
+  struct In {
+    double2 z, s, dz, ds;
+  };
+  double2* Z;
+  double2* S;
+  double2* DZ;
+  double2* DS;
+  double aP, aD, z0, s0;
+  int mode;
+  double acc[K];
+  __device__ void reset() { acc[0] = acc[1] = 0.0; }
+  __device__ void load(long i, In& in) const {
+    if (mode != RA_INIT) {
+      in.z = Z[i];
+      in.s = S[i];
+    }
+    if (mode == RA_STEP || mode == RA_TRIAL) {
+      in.dz = DZ[i];
+      in.ds = DS[i];
+    }
+  }
+  __device__ double gather(long i, const In& in) {
+    double2 z, s;
+    if (mode == RA_INIT) {
+      z = make_double2(z0, z0);
+      s = make_double2(s0, s0);
+    } else if (mode == RA_NONE) {
+      z = in.z;
+      s = in.s;
+    } else {
+      z = make_double2(in.z.x + aP * in.dz.x, in.z.y + aP * in.dz.y);
+      s = make_double2(in.s.x + aD * in.ds.x, in.s.y + aD * in.ds.y);
+    }
+    if (mode == RA_INIT || mode == RA_STEP) {
+      Z[i] = z;
+      S[i] = s;
+    }
+    acc[0] += z.x + z.y;
+    acc[1] += z.x * s.x + z.y * s.y;
+    return z.x - z.y;
+  }
+};
+
+// Residual pass C: with g = A^T (A x - b) build the Newton right-hand side
+// rhs = f_z + Z^{-1} f_s, f_z = s - [tau + g; tau - g], f_s = sigma mu - z s
+// (eqs. (fzfs), (redNewtonA)); store Theta^{-1} = s / z (not at the trial
+// point), r = rhs, x = 0.  acc0 = max |g|, acc1 += rhs^T rhs,
+// acc2 += rhs^T P^{-1} rhs.
+struct FResC {
+  static constexpr int K = 3;
+  struct In {
+    double2 z, s, dz, ds, ti;
+  };
+  double2* Z;
+  double2* S;
+  double2* DZ;
+  double2* DS;
+  double2* TI;
+  double2* R;
+  double2* X;
+  double tau, sigma, mu, aP, aD, rho;
+  int trial;
+  double acc[K];
+  __device__ void reset() {
+    acc[0] = -__builtin_inf();
+    acc[1] = acc[2] = 0.0;
+  }
+  __device__ void load(long i, In& in) const {
+    in.z = Z[i];
+    in.s = S[i];
+    if (trial) {
+      in.dz = DZ[i];
+      in.ds = DS[i];
+      in.ti = TI[i];
+    }
+  }
+  __device__ void scatter(long i, double g, const In& in) {
+    double2 zt = in.z, st = in.s, ti;
+    if (trial) {
+      zt = make_double2(in.z.x + aP * in.dz.x, in.z.y + aP * in.dz.y);
+      st = make_double2(in.s.x + aD * in.ds.x, in.s.y + aD * in.ds.y);
+      ti = in.ti;
+    } else {
+      ti = make_double2(in.s.x / in.z.x, in.s.y / in.z.y);
+      TI[i] = ti;
+    }
+    const double fzu = st.x - (tau + g), fzv = st.y - (tau - g);
+    const double fsu = sigma * mu - zt.x * st.x, fsv = sigma * mu - zt.y * st.y;
+    const double ru = fzu + fsu / in.z.x, rv = fzv + fsv / in.z.y;
+    R[i] = make_double2(ru, rv);
+    X[i] = make_double2(0.0, 0.0);
+    acc[0] = fmax(acc[0], fabs(g));
+    acc[1] += ru * ru + rv * rv;
+    double yu, yv;
+    precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
+    acc[2] += ru * yu + rv * yv;
+  }
+};
+
+// Step pass (elementwise).  Predictor: ds = f_s / z - Theta^{-1} dz
+// (eq. (redNewtonB)), store DZ, DS.  Corrector: the same at the trial point
+// with sigma3, added to the stored predictor direction.  acc0 = min ratio
+// over dz < 0 of -z/dz, acc1 likewise for s.
+struct FStep {
+  static constexpr int K = 2;
+  struct In {
+    double2 z, s, ti, x, dz, ds;
+  };
+  double2* Z;
+  double2* S;
+  double2* TI;
+  double2* X;
+  double2* DZ;
+  double2* DS;
+  double sigma, mu;      // predictor: sigma, mu; corrector: sigma3, mu~
+  double aPp, aDp;       // predictor step sizes (corrector only)
+  int corr;
+  double acc[K];
+  __device__ void reset() { acc[0] = acc[1] = __builtin_inf(); }
+  __device__ void load(long i, In& in) const {
+    in.z = Z[i];
+    in.s = S[i];
+    in.ti = TI[i];
+    in.x = X[i];
+    if (corr) {
+      in.dz = DZ[i];
+      in.ds = DS[i];
+    }
+  }
+  __device__ void elem(long i, const In& in) {
+    double2 dz, ds;
+    if (!corr) {
+      dz = in.x;
+      const double fsu = sigma * mu - in.z.x * in.s.x, fsv = sigma * mu - in.z.y * in.s.y;
+      ds = make_double2(fsu / in.z.x - in.ti.x * dz.x, fsv / in.z.y - in.ti.y * dz.y);
+    } else {
+      const double ztu = in.z.x + aPp * in.dz.x, ztv = in.z.y + aPp * in.dz.y;
+      const double stu = in.s.x + aDp * in.ds.x, stv = in.s.y + aDp * in.ds.y;
+      const double fsu = sigma * mu - ztu * stu, fsv = sigma * mu - ztv * stv;
+      const double dsu = fsu / in.z.x - in.ti.x * in.x.x, dsv = fsv / in.z.y - in.ti.y * in.x.y;
+      dz = make_double2(in.dz.x + in.x.x, in.dz.y + in.x.y);
+      ds = make_double2(in.ds.x + dsu, in.ds.y + dsv);
+    }
+    DZ[i] = dz;
+    DS[i] = ds;
+    if (dz.x < 0) acc[0] = fmin(acc[0], -in.z.x / dz.x);
+    if (dz.y < 0) acc[0] = fmin(acc[0], -in.z.y / dz.y);
+    if (ds.x < 0) acc[1] = fmin(acc[1], -in.s.x / ds.x);
+    if (ds.y < 0) acc[1] = fmin(acc[1], -in.s.y / ds.y);
+  }
+};
+
+// Output pass: x = u - v.
+struct FOut {
+  static constexpr int K = 1;
+  struct In {
+    double2 z;
+  };
+  double2* Z;
+  double* x;
+  double acc[K];
+  __device__ void reset() { acc[0] = 0.0; }
+  __device__ void load(long i, In& in) const { in.z = Z[i]; }
+  __device__ void elem(long i, const In& in) { x[i] = in.z.x - in.z.y; }
+};
+
+// Adjoint set-up: Theta^{-1} = s / z at the given state, r = rhs = [g; -g],
+// x = 0.  acc0 += rhs^T rhs, acc1 += rhs^T P^{-1} rhs.
+struct FBwdInit {
+  static constexpr int K = 2;
+  struct In {
+    double2 z, s;
+    double g;
+  };
+  const double2* Z;
+  const double2* S;
+  const double* gx;
+  double2* TI;
+  double2* R;
+  double2* X;
+  double rho;
+  double acc[K];
+  __device__ void reset() { acc[0] = acc[1] = 0.0; }
+  __device__ void load(long i, In& in) const {
+    in.z = Z[i];
+    in.s = S[i];
+    in.g = gx[i];
+  }
+  __device__ void elem(long i, const In& in) {
+    const double2 ti = make_double2(in.s.x / in.z.x, in.s.y / in.z.y);
+    TI[i] = ti;
+    const double ru = in.g, rv = -in.g;
+    R[i] = make_double2(ru, rv);
+    X[i] = make_double2(0.0, 0.0);
+    double yu, yv;
+    precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
+    acc[0] += ru * ru + rv * rv;
+    acc[1] += ru * yu + rv * yv;
+  }
+};
+
+// Adjoint output gather: d = w_u - w_v; acc0 += 1^T w.
+struct FBwdGather {
+  static constexpr int K = 1;
+  struct In {
+    double2 w;
+  };
+  double2* W;
+  double acc[K];
+  __device__ void reset() { acc[0] = 0.0; }
+  __device__ void load(long i, In& in) const { in.w = W[i]; }
+  __device__ double gather(long i, const In& in) {
+    acc[0] += in.w.x + in.w.y;
+    return in.w.x - in.w.y;
+  }
+};
+
+// ------------------------------------------------------------------------
+// pass runners
+// ------------------------------------------------------------------------
+struct Ctx {
+  Team t;
+  double* red;  // LDS reduction scratch (MF_RED_DOUBLES doubles)
+};
+
+template <int K>
+__device__ __forceinline__ void kinds_fill(int (&k)[K], int a, int b = 0, int c = 0, int d = 0) {
+  const int v[4] = {a, b, c, d};
+#pragma unroll
+  for (int j = 0; j < K; ++j) k[j] = v[j];
+}
+
+template <class F>
+__device__ __forceinline__ void finish_item(Ctx& cx, F& f, const int (&kinds)[F::K], double* part, int item) {
+  double v[F::K];
+#pragma unroll
+  for (int j = 0; j < F::K; ++j) v[j] = f.acc[j];
+  wg_reduce<F::K>(kinds, v, cx.red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < F::K; ++j) part[(long)item * MF_MAXK + j] = v[j];
+  }
+}
+
+template <class OP, class F>
+__device__ void run_A(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
+  const int ni = op.nA();
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    f.reset();
+    op.passA(it, f);
+    finish_item(cx, f, kinds, part, it);
+  }
+}
+
+template <class OP, class F>
+__device__ void run_C(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
+  const int ni = op.nC();
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    f.reset();
+    op.passC(it, f);
+    finish_item(cx, f, kinds, part, it);
+  }
+}
+
+// pass B: two sums (y^2, b.y)
+template <class OP>
+__device__ void run_B(Ctx& cx, OP& op, int mode, double* part, double* out);
+
+template <>
+__device__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, double* out) {
+  const int ni = op.nB();
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    double acc[2] = {0.0, 0.0};
+    op.passB(it, mode, acc, out);
+    if (threadIdx.x == 0) {
+      part[(long)it * MF_MAXK + 0] = acc[0];
+      part[(long)it * MF_MAXK + 1] = acc[1];
+    }
+  }
+}
+
+template <>
+__device__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*) {
+  const int ni = op.nB();
+  const int kinds[2] = {0, 0};
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    double acc[2] = {0.0, 0.0};
+    op.passB(it, mode, acc);
+    wg_reduce<2>(kinds, acc, cx.red);
+    if (threadIdx.x == 0) {
+      part[(long)it * MF_MAXK + 0] = acc[0];
+      part[(long)it * MF_MAXK + 1] = acc[1];
+    }
+  }
+}
+
+// elementwise pass over [0, n), items of 1024 indices
+template <class F>
+__device__ void run_E(Ctx& cx, long n, F& f, const int (&kinds)[F::K], double* part) {
+  const int ni = (int)((n + 1023) / 1024);
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    f.reset();
+    const long base = (long)it * 1024;
+    constexpr int U = 1024 / MF_THREADS;
+    typename F::In in[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long i = base + threadIdx.x + k * MF_THREADS;
+      if (i < n) f.load(i, in[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long i = base + threadIdx.x + k * MF_THREADS;
+      if (i < n) f.elem(i, in[k]);
+    }
+    finish_item(cx, f, kinds, part, it);
+  }
+}
+__device__ __forceinline__ int nE(long n) { return (int)((n + 1023) / 1024); }
+
+// ------------------------------------------------------------------------
+// Operator construction and set-up
+// ------------------------------------------------------------------------
+__device__ inline void make_op(OpDense& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+  op.n = d.n;
+  op.m = d.m;
+  op.lda = d.n;
+  op.A = a.A + (a.shared_op ? 0 : d.a_off);
+  op.b = a.b ? a.b + d.m_off : nullptr;
+  op.D = w.D;
+  op.Yv = w.Yv;
+  op.RB = a.tile_param > 0 ? (a.tile_param > DN_RBMAX ? DN_RBMAX : a.tile_param) : 8;
+  op.lds = (double*)lds;
+}
+
+__device__ inline int ilog2(long v) {
+  int l = 0;
+  while ((1L << l) < v) ++l;
+  return l;
+}
+
+__device__ inline void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+  op.n = d.n;
+  op.m = d.m;
+  op.H = (int)(d.n >> 1);
+  op.logn = ilog2(d.n);
+  const int lh = op.logn - 1;
+  int l1 = lh / 2;
+  if (a.tile_param > 0) l1 = a.tile_param;
+  if (l1 > 9) l1 = 9;
+  if (lh - l1 > 11) l1 = lh - 11;
+  if (lh - l1 < 3) l1 = lh - 3;
+  op.l1 = l1;
+  op.l2 = lh - l1;
+  op.N1 = 1 << op.l1;
+  op.N2 = 1 << op.l2;
+  op.rows = a.rows + (a.shared_op ? 0 : d.m_off);
+  op.b = a.b ? a.b + d.m_off : nullptr;
+  op.Y1 = w.Y1;
+  op.Y2 = w.Y2;
+  op.mask = w.mask;
+  op.bt = w.bt;
+  op.XS = w.XS;
+  op.tw.lo = a.tw_lo;
+  op.tw.hi = a.tw_hi;
+  op.tw.lo_bits = a.tw_lo_bits;
+  op.tw.scale_shift = a.tw_log2n_max - op.logn;
+  op.tile = (cplx*)lds;
+  op.a0 = sqrt(1.0 / (double)d.n);
+  op.a1 = sqrt(2.0 / (double)d.n);
+}
+
+// Dense set-up: nothing to build.  Returns 0 (ok) or ST_ABORTED.
+__device__ inline int op_setup(Ctx& cx, OpDense&, const KArgs&, const TeamWS&, int) { return 0; }
+
+// PDCT set-up: zero the spectral mask / b~, then scatter the sampled rows
+// (checking they are sorted, distinct and in range).  with_b = 0 skips b~.
+__device__ inline int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS& w, int with_b) {
+  const long n = op.n;
+  const long nthr = (long)cx.t.size * MF_THREADS;
+  const long gt = (long)cx.t.rank * MF_THREADS + threadIdx.x;
+  if (gt == 0) *w.err = 0;
+  for (long i = gt; i < n; i += nthr) {
+    w.mask[i] = 0;
+    w.bt[i] = 0.0;
+  }
+  if (team_barrier(cx.t)) return ST_ABORTED;
+  int bad = 0;
+  for (long i = gt; i < op.m; i += nthr) {
+    const long kk = op.rows[i];
+    if (kk < 0 || kk >= n || (i > 0 && op.rows[i - 1] >= kk)) {
+      bad = 1;
+      continue;
+    }
+    const long p = op.coef_pos(kk);
+    w.mask[p] = 1;
+    if (with_b) w.bt[p] = op.b[i];
+  }
+  if (bad) __hip_atomic_store(w.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (team_barrier(cx.t)) return ST_ABORTED;
+  if (ld_flag(w.err)) return ST_DEVICE_CHECK;
+  return 0;
+}
+
+// rho: Frobenius-closest scalar to A^T A (Section 5, before eq. (eq:ne2_P)).
+__device__ inline double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
+  const int ni = op.nB();
+  for (int it = cx.t.rank; it < ni; it += cx.t.size) {
+    const double s = op.frob_block(it);
+    if (threadIdx.x == 0) w.partS[(long)it * MF_MAXK] = s;
+  }
+  ab = team_barrier(cx.t);
+  const int kinds[1] = {0};
+  double r[1];
+  reduce_items<1>(kinds, w.partS, ni, r, cx.red);
+  return r[0] / (double)op.n;
+}
+__device__ inline double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& ab) {
+  ab = 0;
+  return (double)op.m / (double)op.n;  // orthonormal rows: ||A||_F^2 = m
+}
+
+// ------------------------------------------------------------------------
+// PCG on (Theta^{-1} + F F^T) x = rhs with the block preconditioner.
+// On entry R = rhs, X = 0, TI set; rhs2 = rhs^T rhs, rty = rhs^T P^{-1} rhs.
+// Returns a status (0 = ok); *iters = operator applies.
+// ------------------------------------------------------------------------
+template <class OP>
+__device__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit, double rhs2,
+                       double rty, int* iters) {
+  const int kA[1] = {0};
+  const int kC[2] = {0, 0};
+  double rr = rhs2, rty_prev = 1.0;
+  int it = 0, status = 0;
+  for (;;) {
+    if (!isfinite(rr)) {
+      status = ST_NONFINITE;
+      break;
+    }
+    if (rr <= tol * tol * rhs2) break;
+    if (it == maxit) break;
+    FPcgA fa;
+    fa.R = w.R;
+    fa.TI = w.TI;
+    fa.P = w.P;
+    fa.rho = rho;
+    fa.first = (it == 0);
+    fa.beta = it == 0 ? 0.0 : rty / rty_prev;
+    run_A(cx, op, fa, kA, w.partA);
+    if (team_barrier(cx.t)) {
+      status = ST_ABORTED;
+      break;
+    }
+    double pA[1];
+    reduce_items<1>(kA, w.partA, op.nA(), pA, cx.red);
+    run_B<OP>(cx, op, 0, w.partB, nullptr);
+    if (team_barrier(cx.t)) {
+      status = ST_ABORTED;
+      break;
+    }
+    double pB[1];
+    {
+      const int kb[1] = {0};
+      reduce_items<1>(kb, w.partB, op.nB(), pB, cx.red);
+    }
+    ++it;
+    const double pq = pA[0] + pB[0];
+    if (!(pq > 0.0)) {
+      status = isfinite(pq) ? ST_PCG_BREAKDOWN : ST_NONFINITE;
+      break;
+    }
+    FPcgC fc;
+    fc.P = w.P;
+    fc.TI = w.TI;
+    fc.X = w.X;
+    fc.R = w.R;
+    fc.rho = rho;
+    fc.alpha = rty / pq;
+    run_C(cx, op, fc, kC, w.partC);
+    if (team_barrier(cx.t)) {
+      status = ST_ABORTED;
+      break;
+    }
+    double pC[2];
+    reduce_items<2>(kC, w.partC, op.nC(), pC, cx.red);
+    rty_prev = rty;
+    rty = pC[0];
+    rr = pC[1];
+  }
+  *iters = it;
+  return status;
+}
+
+// Residual evaluation at the current point (after the pending update given by
+// mode/aP/aD) or at the trial point: computes the gap terms and the Newton
+// right-hand side for sigma (and mu = z^T s/(2n) at that point).
+struct ResOut {
+  double sumz, zs, rb2, brb, ginf, rhs2, rty;
+  int status;
+};
+
+template <class OP>
+__device__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w, double2* Z, double2* S, const DevParams& prm,
+                               int mode, double aP, double aD, double tau, double sigma, double sigma3,
+                               int trial, double rho) {
+  ResOut o;
+  o.status = 0;
+  FResA fa;
+  fa.Z = Z;
+  fa.S = S;
+  fa.DZ = w.DZ;
+  fa.DS = w.DS;
+  fa.aP = aP;
+  fa.aD = aD;
+  fa.z0 = prm.z0;
+  fa.s0 = prm.s0;
+  fa.mode = mode;
+  const int kA[2] = {0, 0};
+  run_A(cx, op, fa, kA, w.partA);
+  if (team_barrier(cx.t)) {
+    o.status = ST_ABORTED;
+    return o;
+  }
+  double pA[2];
+  reduce_items<2>(kA, w.partA, op.nA(), pA, cx.red);
+  o.sumz = pA[0];
+  o.zs = pA[1];
+  run_B<OP>(cx, op, 1, w.partB, nullptr);
+  if (team_barrier(cx.t)) {
+    o.status = ST_ABORTED;
+    return o;
+  }
+  double pB[2];
+  {
+    const int kb[2] = {0, 0};
+    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
+  }
+  o.rb2 = pB[0];
+  o.brb = pB[1];
+  FResC fc;
+  fc.Z = Z;
+  fc.S = S;
+  fc.DZ = w.DZ;
+  fc.DS = w.DS;
+  fc.TI = w.TI;
+  fc.R = w.R;
+  fc.X = w.X;
+  fc.tau = tau;
+  fc.sigma = trial ? sigma3 : sigma;
+  fc.mu = o.zs / (2.0 * (double)op.n);
+  fc.aP = aP;
+  fc.aD = aD;
+  fc.rho = rho;
+  fc.trial = trial;
+  const int kC[3] = {1, 0, 0};
+  run_C(cx, op, fc, kC, w.partC);
+  if (team_barrier(cx.t)) {
+    o.status = ST_ABORTED;
+    return o;
+  }
+  double pC[3];
+  reduce_items<3>(kC, w.partC, op.nC(), pC, cx.red);
+  o.ginf = pC[0];
+  o.rhs2 = pC[1];
+  o.rty = pC[2];
+  return o;
+}
+
+template <class OP>
+__device__ void solve_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
+  const InstDesc d = a.inst[ii];
+  const TeamWS w = make_ws(a, cx.t.id);
+  const DevParams& prm = a.prm;
+  OP op;
+  make_op(op, a, d, w, lds);
+  const long n = d.n;
+  double2* Z = a.state ? (double2*)(a.state + 4 * d.n_off) : w.Zs;
+  double2* S = a.state ? (double2*)(a.state + 4 * d.n_off + 2 * d.n) : w.Ss;
+  const double tau = d.tau;
+
+  int status = ST_MAXITER;
+  int k = 1, pcg_total = 0, ncorr = 0;
+  long nmat = 0;
+  double relgap = __builtin_nan(""), mu = 0.0, primal = 0.0, dual = 0.0, rho = prm.rho;
+  int st = op_setup(cx, op, a, w, 1);
+  if (st) status = st;
+  if (!st && !(prm.rho > 0.0)) {
+    int ab = 0;
+    rho = op_rho(cx, op, w, ab);
+    if (ab) st = status = ST_ABORTED;
+  }
+  if (!st) {
+    double aP_prev = 1.0, aD_prev = 1.0, aP = 0.0, aD = 0.0;
+    int mode = RA_INIT;
+    const int kS[2] = {2, 2};
+    for (;;) {
+      // sigma for this iteration from the previous step sizes
+      const double sigma = (k != 1 && (aP_prev <= prm.alpha_bar || aD_prev <= prm.alpha_bar)) ? prm.sigma2
+                                                                                               : prm.sigma1;
+      ResOut ro = residual_rhs(cx, op, w, Z, S, prm, mode, aP, aD, tau, sigma, prm.sigma3, 0, rho);
+      nmat += 2;
+      if (ro.status) {
+        status = ro.status;
+        break;
+      }
+      mu = ro.zs / (2.0 * (double)n);
+      primal = tau * ro.sumz + 0.5 * ro.rb2;
+      const double theta = ro.ginf <= tau ? 1.0 : tau / ro.ginf;
+      dual = -0.5 * theta * theta * ro.rb2 - theta * ro.brb;
+      relgap = (primal - dual) / (1.0 + fabs(primal));
+      if (!isfinite(relgap)) {
+        status = ST_NONFINITE;
+        break;
+      }
+      if (relgap <= prm.tol) {
+        status = ST_CONVERGED;
+        break;
+      }
+      if (k > prm.maxiters) {
+        status = ST_MAXITER;
+        break;
+      }
+      int its = 0;
+      st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, &its);
+      pcg_total += its;
+      nmat += 2 * its;
+      if (st) {
+        status = st;
+        break;
+      }
+      FStep fs;
+      fs.Z = Z;
+      fs.S = S;
+      fs.TI = w.TI;
+      fs.X = w.X;
+      fs.DZ = w.DZ;
+      fs.DS = w.DS;
+      fs.sigma = sigma;
+      fs.mu = mu;
+      fs.corr = 0;
+      fs.aPp = fs.aDp = 0.0;
+      run_E(cx, n, fs, kS, w.partS);
+      if (team_barrier(cx.t)) {
+        status = ST_ABORTED;
+        break;
+      }
+      double rs[2];
+      reduce_items<2>(kS, w.partS, nE(n), rs, cx.red);
+      aP = fmin(1.0, prm.eta * rs[0]);
+      aD = fmin(1.0, prm.eta * rs[1]);
+      if (aP <= prm.alpha_tilde || aD <= prm.alpha_tilde) {
+        // corrector: residuals at the trial point with sigma3, same H and P
+        ResOut rc = residual_rhs(cx, op, w, Z, S, prm, RA_TRIAL, aP, aD, tau, sigma, prm.sigma3, 1, rho);
+        nmat += 2;
+        if (rc.status) {
+          status = rc.status;
+          break;
+        }
+        st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, &its);
+        pcg_total += its;
+        nmat += 2 * its;
+        if (st) {
+          status = st;
+          break;
+        }
+        fs.sigma = prm.sigma3;
+        fs.mu = rc.zs / (2.0 * (double)n);
+        fs.corr = 1;
+        fs.aPp = aP;
+        fs.aDp = aD;
+        run_E(cx, n, fs, kS, w.partS);
+        if (team_barrier(cx.t)) {
+          status = ST_ABORTED;
+          break;
+        }
+        reduce_items<2>(kS, w.partS, nE(n), rs, cx.red);
+        aP = fmin(1.0, prm.eta * rs[0]);
+        aD = fmin(1.0, prm.eta * rs[1]);
+        ++ncorr;
+      }
+      if (aP < prm.step_min && aD < prm.step_min) {
+        status = ST_STEP_UNDERFLOW;
+        break;
+      }
+      mode = RA_STEP;
+      aP_prev = aP;
+      aD_prev = aD;
+      ++k;
+    }
+    // x = u - v
+    FOut fo;
+    fo.Z = Z;
+    fo.x = a.x + d.n_off;
+    const int kO[1] = {0};
+    run_E(cx, n, fo, kO, w.partS);
+  }
+  if (cx.t.rank == 0 && threadIdx.x == 0) {
+    DevInfo inf;
+    inf.status = status;
+    inf.ipm_iters = k - 1;
+    inf.pcg_iters = pcg_total;
+    inf.correctors = ncorr;
+    inf.nmat = nmat;
+    inf.rel_gap = relgap;
+    inf.mu = mu;
+    inf.primal_obj = primal;
+    inf.dual_obj = dual;
+    inf.rho = rho;
+    a.info[ii] = inf;
+  }
+}
+
+// Forward product y = A d after a pass A that left d in the operator's
+// buffers: dense writes y directly; the partial DCT writes the spectral
+// coefficients (pass B) and then gathers the sampled rows.
+__device__ inline void op_forward_out(Ctx& cx, OpDense& op, const TeamWS& w, double* out) {
+  run_B<OpDense>(cx, op, DB_OUT, w.partB, out);
+}
+__device__ inline void op_forward_gather(Ctx&, OpDense&, const TeamWS&, double*) {}
+__device__ inline void op_forward_out(Ctx& cx, OpPdct& op, const TeamWS& w, double*) {
+  run_B<OpPdct>(cx, op, PB_FWDOUT, w.partB, nullptr);
+}
+__device__ inline void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, double* out) {
+  const long nthr = (long)cx.t.size * MF_THREADS;
+  for (long i = (long)cx.t.rank * MF_THREADS + threadIdx.x; i < op.m; i += nthr)
+    out[i] = w.XS[op.coef_pos(op.rows[i])];
+}
+
+// Adjoint: (Theta^{-1} + F F^T) w = [g; -g] at the stored state, then
+// grad_b = A (w_u - w_v), grad_tau = -1^T w.
+template <class OP>
+__device__ void backward_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
+  const InstDesc d = a.inst[ii];
+  const TeamWS w = make_ws(a, cx.t.id);
+  const DevParams& prm = a.prm;
+  OP op;
+  make_op(op, a, d, w, lds);
+  const long n = d.n;
+  const double2* Z = (const double2*)(a.state + 4 * d.n_off);
+  const double2* S = (const double2*)(a.state + 4 * d.n_off + 2 * d.n);
+  int status = 0, its = 0;
+  double rho = prm.rho, gtau = 0.0;
+  int st = op_setup(cx, op, a, w, 0);
+  if (st) status = st;
+  if (!st && !(prm.rho > 0.0)) {
+    int ab = 0;
+    rho = op_rho(cx, op, w, ab);
+    if (ab) st = status = ST_ABORTED;
+  }
+  if (!st) {
+    FBwdInit fi;
+    fi.Z = Z;
+    fi.S = S;
+    fi.gx = a.grad_x + d.n_off;
+    fi.TI = w.TI;
+    fi.R = w.R;
+    fi.X = w.X;
+    fi.rho = rho;
+    const int kI[2] = {0, 0};
+    run_E(cx, n, fi, kI, w.partS);
+    if (team_barrier(cx.t)) st = ST_ABORTED;
+    double pI[2];
+    reduce_items<2>(kI, w.partS, nE(n), pI, cx.red);
+    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[0], pI[1], &its);
+    status = st;
+    if (!st || st == ST_PCG_BREAKDOWN) {
+      FBwdGather fg;
+      fg.W = w.X;
+      const int kG[1] = {0};
+      run_A(cx, op, fg, kG, w.partA);
+      if (team_barrier(cx.t)) status = ST_ABORTED;
+      double pG[1];
+      reduce_items<1>(kG, w.partA, op.nA(), pG, cx.red);
+      gtau = -pG[0];
+      if (!status) {
+        op_forward_out(cx, op, w, a.grad_b + d.m_off);
+        if (team_barrier(cx.t)) status = ST_ABORTED;
+        if (!status) op_forward_gather(cx, op, w, a.grad_b + d.m_off);
+      }
+    }
+  }
+  if (cx.t.rank == 0 && threadIdx.x == 0) {
+    a.grad_tau[ii] = gtau;
+    DevInfo inf;
+    inf.status = status;
+    inf.ipm_iters = 0;
+    inf.pcg_iters = its;
+    inf.correctors = 0;
+    inf.nmat = 2L * its + 2;
+    inf.rel_gap = 0.0;
+    inf.mu = 0.0;
+    inf.primal_obj = 0.0;
+    inf.dual_obj = 0.0;
+    inf.rho = rho;
+    a.info[ii] = inf;
+  }
+}

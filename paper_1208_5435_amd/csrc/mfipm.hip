@@ -1,0 +1,546 @@
+// mfipm.hip -- persistent HIP kernels and the C ABI of the matrix-free IPM
+// solver for l1-regularised least squares (declared in include/mfipm.h).
+//
+// One cooperative launch per call.  The grid is split into teams of
+// workgroups; each team takes instances from a device queue (host order:
+// largest first) and runs the whole IPM of one instance -- residuals, PCG,
+// step lengths, corrector, update -- with team barriers between passes.  The
+// host only reads the per-instance reports after the kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/mfipm.h"
+#include "ipm.h"
+
+static_assert(sizeof(DevParams) == sizeof(mfipm_params), "params mirror");
+static_assert(sizeof(DevInfo) == sizeof(mfipm_info), "info mirror");
+
+// ------------------------------------------------------------------------
+// kernels
+// ------------------------------------------------------------------------
+template <class OP, int BWD>
+__global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds_dyn[];
+  __shared__ double red[MF_RED_DOUBLES];
+  Ctx cx;
+  cx.red = red;
+  cx.t.size = a.team_size;
+  cx.t.id = blockIdx.x / a.team_size;
+  cx.t.rank = blockIdx.x % a.team_size;
+  cx.t.gen = 0;
+  cx.t.abort_flag = a.abort_flag;
+  cx.t.spin_ticks = a.spin_ticks;
+  const TeamWS w = make_ws(a, cx.t.id);
+  cx.t.bar = w.bar;
+  for (;;) {
+    // the previous slot value has been read by every workgroup of the team
+    if (team_barrier(cx.t)) break;
+    if (cx.t.rank == 0 && threadIdx.x == 0) {
+      const int q = __hip_atomic_fetch_add(a.queue_head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(w.slot, q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (team_barrier(cx.t)) break;
+    const int q = ld_flag(w.slot);
+    if (q >= a.batch) break;
+    const int ii = a.order[q];
+    if (BWD) backward_instance<OP>(cx, a, ii, lds_dyn);
+    else solve_instance<OP>(cx, a, ii, lds_dyn);
+  }
+}
+
+// ------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------
+struct mfipm_handle {
+  mfipm_params prm;
+  hipStream_t stream;
+  int device;
+  int num_cu;
+  long long wall_khz;
+  int req_wg, req_team, req_tile;
+  hipEvent_t ev0, ev1;
+  double last_ms;
+  int occ[2][2];  // [op][bwd] max resident workgroups per CU
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int check_params(const mfipm_params* p) {
+  if (!p) return MFIPM_ERR_INVALID_ARG;
+  if (!(p->tol > 0) || p->maxiters < 1 || !(p->tolpcg > 0) || p->mxiterpcg < 1) return MFIPM_ERR_INVALID_ARG;
+  if (!(p->eta > 0 && p->eta <= 1) || !(p->z0 > 0) || !(p->s0 > 0)) return MFIPM_ERR_INVALID_ARG;
+  if (!(p->tolpcg_adj > 0) || p->mxiterpcg_adj < 1 || !(p->step_min >= 0)) return MFIPM_ERR_INVALID_ARG;
+  if (!(p->sigma1 >= 0 && p->sigma1 <= 1 && p->sigma2 >= 0 && p->sigma2 <= 1 && p->sigma3 >= 0 &&
+        p->sigma3 <= 1))
+    return MFIPM_ERR_INVALID_ARG;
+  if (std::isnan(p->rho)) return MFIPM_ERR_INVALID_ARG;
+  return MFIPM_OK;
+}
+
+inline int ilog2_host(long long v) {
+  int l = 0;
+  while ((1LL << l) < v) ++l;
+  return l;
+}
+inline bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Team region layout for the largest instance of a call.
+TeamLayout team_layout(int op_kind, long long n, long long m) {
+  TeamLayout L{};
+  size_t off = 0;
+  auto take = [&](long& field, size_t bytes) {
+    field = (long)off;
+    off += align_up(bytes);
+  };
+  const size_t v2 = (size_t)n * 2 * sizeof(double);
+  take(L.X, v2);
+  take(L.R, v2);
+  take(L.P, v2);
+  take(L.TI, v2);
+  take(L.DZ, v2);
+  take(L.DS, v2);
+  take(L.Zs, v2);
+  take(L.Ss, v2);
+  if (op_kind == MFIPM_OP_DENSE) {
+    take(L.D, (size_t)n * sizeof(double));
+    take(L.Yv, (size_t)m * sizeof(double));
+    L.Y1 = L.Y2 = L.mask = L.bt = L.XS = 0;
+  } else {
+    L.D = L.Yv = 0;
+    take(L.Y1, (size_t)n * sizeof(double));  // n/2 complex
+    take(L.Y2, (size_t)n * sizeof(double));
+    take(L.mask, (size_t)n);
+    take(L.bt, (size_t)n * sizeof(double));
+    take(L.XS, (size_t)n * sizeof(double));
+  }
+  const size_t items = (size_t)(n + m + 64);
+  const size_t pb = items * MF_MAXK * sizeof(double);
+  take(L.partA, pb);
+  take(L.partB, pb);
+  take(L.partC, pb);
+  take(L.partS, pb);
+  take(L.ctl, 256);
+  L.stride = (long)off;
+  return L;
+}
+
+struct GlobalLayout {
+  size_t ctl, info, inst, order, tw_lo, tw_hi, teams, total;
+  int lo_bits;
+  long long hi_count;
+};
+
+GlobalLayout global_layout(int op_kind, long long n_max, int batch, int teams, const TeamLayout& tl) {
+  GlobalLayout g{};
+  size_t off = 0;
+  g.ctl = off;
+  off += align_up(256);
+  g.info = off;
+  off += align_up((size_t)batch * sizeof(DevInfo));
+  g.inst = off;
+  off += align_up((size_t)batch * sizeof(InstDesc));
+  g.order = off;
+  off += align_up((size_t)batch * sizeof(int));
+  g.lo_bits = 0;
+  g.hi_count = 0;
+  g.tw_lo = g.tw_hi = off;
+  if (op_kind == MFIPM_OP_PDCT) {
+    const int lm = ilog2_host(n_max) + 2;  // table resolution 4 n_max
+    g.lo_bits = (lm + 1) / 2;
+    g.hi_count = 1LL << (lm - g.lo_bits);
+    g.tw_lo = off;
+    off += align_up(((size_t)1 << g.lo_bits) * sizeof(cplx));
+    g.tw_hi = off;
+    off += align_up((size_t)g.hi_count * sizeof(cplx));
+  }
+  g.teams = off;
+  off += (size_t)teams * (size_t)tl.stride;
+  g.total = off;
+  return g;
+}
+
+int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch) {
+  const int gmax = std::max(1, h->occ[op_kind][bwd] * h->num_cu);
+  return std::max(1, std::min(batch, gmax));
+}
+
+template <class OP, int BWD>
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&k_mfipm<OP, BWD>);
+}
+const void* pick_kernel(int op_kind, int bwd) {
+  if (op_kind == MFIPM_OP_DENSE) return bwd ? kernel_ptr<OpDense, 1>() : kernel_ptr<OpDense, 0>();
+  return bwd ? kernel_ptr<OpPdct, 1>() : kernel_ptr<OpPdct, 0>();
+}
+size_t dyn_lds(int op_kind) {
+  return op_kind == MFIPM_OP_DENSE ? (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double)
+                                   : (size_t)PD_TILE_CPLX * sizeof(cplx);
+}
+
+void fill_twiddles(std::vector<cplx>& lo, std::vector<cplx>& hi, int lm, int lo_bits) {
+  // T(e) = exp(-2 pi i e / 2^lm) = hi[e >> lo_bits] * lo[e & mask]
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  const long double M = (long double)(1LL << lm);
+  lo.resize((size_t)1 << lo_bits);
+  hi.resize((size_t)1 << (lm - lo_bits));
+  for (size_t e = 0; e < lo.size(); ++e) {
+    const long double ang = two_pi * (long double)e / M;
+    lo[e] = cplx{(double)cosl(ang), (double)-sinl(ang)};
+  }
+  for (size_t e = 0; e < hi.size(); ++e) {
+    const long double ang = two_pi * (long double)(e << lo_bits) / M;
+    hi[e] = cplx{(double)cosl(ang), (double)-sinl(ang)};
+  }
+}
+
+// Items of the widest pass of one instance (used to size a single team).
+long long widest_pass(int op_kind, long long n, long long m, int tile) {
+  if (op_kind == MFIPM_OP_DENSE) {
+    const int RB = tile > 0 ? std::min(tile, DN_RBMAX) : 8;
+    return std::max((m + RB - 1) / RB, (n + DN_CB - 1) / DN_CB);
+  }
+  const int lh = ilog2_host(n) - 1;
+  int l1 = tile > 0 ? tile : lh / 2;
+  l1 = std::min(l1, 9);
+  if (lh - l1 > 11) l1 = lh - 11;
+  if (lh - l1 < 3) l1 = lh - 3;
+  const long long N1 = 1LL << l1, N2 = 1LL << (lh - l1);
+  return std::max(N1 / 2, N2 / 8);
+}
+
+struct Problem {
+  int batch;
+  int op_kind;
+  int shared_op;
+  const int64_t* n_off;
+  const int64_t* m_off;
+  const int64_t* a_off;
+  const double* tau;  // host
+  long long n_max, m_max;
+};
+
+int validate(const mfipm_handle* h, const Problem& P) {
+  if (!h) return MFIPM_ERR_INVALID_ARG;
+  if (P.batch < 1 || !P.n_off || !P.m_off) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind != MFIPM_OP_DENSE && P.op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind == MFIPM_OP_DENSE && !P.shared_op && !P.a_off) return MFIPM_ERR_INVALID_ARG;
+  for (int i = 0; i < P.batch; ++i) {
+    const long long n = P.n_off[i + 1] - P.n_off[i];
+    const long long m = P.m_off[i + 1] - P.m_off[i];
+    if (n < 1 || m < 1 || P.n_off[i] < 0 || P.m_off[i] < 0) return MFIPM_ERR_INVALID_ARG;
+    if (P.op_kind == MFIPM_OP_PDCT) {
+      if (!is_pow2(n) || n < 64 || n > (1LL << 21) || m > n) return MFIPM_ERR_INVALID_ARG;
+    } else if (!P.shared_op && P.a_off[i + 1] - P.a_off[i] != n * m) {
+      return MFIPM_ERR_INVALID_ARG;
+    }
+    if (P.shared_op && i > 0) {
+      const long long n0 = P.n_off[1] - P.n_off[0], m0 = P.m_off[1] - P.m_off[0];
+      if (n != n0 || m != m0) return MFIPM_ERR_INVALID_ARG;
+    }
+    if (P.tau && !(P.tau[i] > 0 && std::isfinite(P.tau[i]))) return MFIPM_ERR_INVALID_ARG;
+  }
+  return MFIPM_OK;
+}
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    if ((expr) != hipSuccess) return MFIPM_ERR_HIP; \
+  } while (0)
+
+// Shared launch path of solve (bwd = 0) and backward (bwd = 1).
+int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const int32_t* rows, const double* b,
+           double* x, double* state, const double* grad_x, double* grad_b, double* grad_tau, void* ws,
+           size_t ws_bytes, mfipm_info* infos) {
+  int rc = validate(h, P);
+  if (rc) return rc;
+  if (!ws) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind == MFIPM_OP_DENSE && !A) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind == MFIPM_OP_PDCT && !rows) return MFIPM_ERR_INVALID_ARG;
+  if (!bwd && (!b || !x)) return MFIPM_ERR_INVALID_ARG;
+  if (bwd && !state) return MFIPM_ERR_NO_STATE;
+  if (bwd && (!grad_x || !grad_b || !grad_tau)) return MFIPM_ERR_INVALID_ARG;
+
+  // launch shape
+  if (h->occ[P.op_kind][bwd] < 1) return MFIPM_ERR_HIP;
+  const int gmax = std::max(1, h->occ[P.op_kind][bwd] * h->num_cu);
+  int team_size, num_teams;
+  if (P.batch == 1) {
+    long long want = h->req_wg > 0 ? h->req_wg : widest_pass(P.op_kind, P.n_max, P.m_max, h->req_tile);
+    team_size = (int)std::max(1LL, std::min<long long>(want, gmax));
+    num_teams = 1;
+  } else {
+    if (h->req_team > 0) team_size = std::min(h->req_team, gmax);
+    else {
+      team_size = std::max(1, gmax / P.batch);
+      team_size = 1 << (31 - __builtin_clz((unsigned)team_size));
+    }
+    const int total = h->req_wg > 0 ? std::min(h->req_wg, gmax) : gmax;
+    num_teams = std::max(1, std::min(P.batch, total / team_size));
+  }
+  const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch);
+  if (num_teams > teams_bound) num_teams = teams_bound;
+
+  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max);
+  const GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
+  if (ws_bytes < gl.total) return MFIPM_ERR_WORKSPACE_TOO_SMALL;
+
+  char* base = (char*)ws;
+  // host-side tables
+  std::vector<InstDesc> inst(P.batch);
+  std::vector<int> order(P.batch);
+  for (int i = 0; i < P.batch; ++i) {
+    inst[i].n = P.n_off[i + 1] - P.n_off[i];
+    inst[i].m = P.m_off[i + 1] - P.m_off[i];
+    inst[i].n_off = P.n_off[i];
+    inst[i].m_off = P.m_off[i];
+    inst[i].a_off = (P.op_kind == MFIPM_OP_DENSE && !P.shared_op) ? P.a_off[i] : 0;
+    inst[i].tau = P.tau ? P.tau[i] : 0.0;
+  }
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+    const double cu = (double)inst[u].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[u].m : 1);
+    const double cv = (double)inst[v].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[v].m : 1);
+    return cu > cv;
+  });
+  hipStream_t s = h->stream;
+  HIP_TRY(hipMemcpyAsync(base + gl.inst, inst.data(), sizeof(InstDesc) * P.batch, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + gl.order, order.data(), sizeof(int) * P.batch, hipMemcpyHostToDevice, s));
+  std::vector<cplx> lo, hi;
+  int logn_max = ilog2_host(P.n_max);
+  if (P.op_kind == MFIPM_OP_PDCT) {
+    fill_twiddles(lo, hi, logn_max + 2, gl.lo_bits);
+    HIP_TRY(hipMemcpyAsync(base + gl.tw_lo, lo.data(), lo.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + gl.tw_hi, hi.data(), hi.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
+  }
+  // zero the control words: queue head, abort flag, team barriers
+  HIP_TRY(hipMemsetAsync(base + gl.ctl, 0, 256, s));
+  for (int t = 0; t < num_teams; ++t)
+    HIP_TRY(hipMemsetAsync(base + gl.teams + (size_t)t * tl.stride + tl.ctl, 0, 256, s));
+
+  KArgs a{};
+  a.inst = (const InstDesc*)(base + gl.inst);
+  a.order = (const int*)(base + gl.order);
+  a.batch = P.batch;
+  a.queue_head = (int*)(base + gl.ctl);
+  a.abort_flag = (int*)(base + gl.ctl + 64);
+  a.info = (DevInfo*)(base + gl.info);
+  a.A = A;
+  a.rows = rows;
+  a.shared_op = P.shared_op;
+  a.b = b;
+  a.x = x;
+  a.state = state;
+  a.grad_x = grad_x;
+  a.grad_b = grad_b;
+  a.grad_tau = grad_tau;
+  std::memcpy(&a.prm, &h->prm, sizeof(DevParams));
+  a.team_base = base + gl.teams;
+  a.lay = tl;
+  a.tw_lo = (const cplx*)(base + gl.tw_lo);
+  a.tw_hi = (const cplx*)(base + gl.tw_hi);
+  a.tw_lo_bits = gl.lo_bits;
+  a.tw_log2n_max = logn_max;
+  a.team_size = team_size;
+  a.tile_param = h->req_tile;
+  a.spin_ticks = (unsigned long long)h->wall_khz * 1000ull * 5ull;  // 5 s per wait
+
+  void* args[] = {&a};
+  const int grid = num_teams * team_size;
+  HIP_TRY(hipEventRecord(h->ev0, s));
+  if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd), dim3(grid), dim3(MF_THREADS), args,
+                                 (unsigned)dyn_lds(P.op_kind), s) != hipSuccess)
+    return MFIPM_ERR_HIP;
+  HIP_TRY(hipEventRecord(h->ev1, s));
+  std::vector<DevInfo> dinf(P.batch);
+  int ctl[32];
+  HIP_TRY(hipMemcpyAsync(dinf.data(), base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ctl, base + gl.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
+  rc = MFIPM_OK;
+  for (int i = 0; i < P.batch; ++i) {
+    if (dinf[i].status == ST_DEVICE_CHECK) rc = MFIPM_ERR_DEVICE_CHECK;
+    if (infos) std::memcpy(&infos[i], &dinf[i], sizeof(mfipm_info));
+  }
+  if (ctl[16] != 0 && rc == MFIPM_OK) rc = MFIPM_ERR_HIP;  // abort flag (offset 64 B)
+  return rc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------
+extern "C" {
+
+int mfipm_params_default(mfipm_params* p) {
+  if (!p) return MFIPM_ERR_INVALID_ARG;
+  p->tol = 1e-8;
+  p->maxiters = 100;
+  p->tolpcg = 1e-2;
+  p->mxiterpcg = 200;
+  p->sigma1 = 0.1;
+  p->sigma2 = 0.5;
+  p->sigma3 = 0.8;
+  p->alpha_bar = 0.5;
+  p->alpha_tilde = 0.1;
+  p->eta = 0.995;
+  p->rho = 0.0;
+  p->z0 = 1.0;
+  p->s0 = 1.0;
+  p->tolpcg_adj = 1e-12;
+  p->mxiterpcg_adj = 1000;
+  p->step_min = 1e-14;
+  return MFIPM_OK;
+}
+
+int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
+  if (!hp) return MFIPM_ERR_INVALID_ARG;
+  *hp = nullptr;
+  mfipm_params prm;
+  if (p) {
+    if (check_params(p)) return MFIPM_ERR_INVALID_ARG;
+    prm = *p;
+  } else {
+    mfipm_params_default(&prm);
+  }
+  mfipm_handle* h = new (std::nothrow) mfipm_handle();
+  if (!h) return MFIPM_ERR_HIP;
+  h->prm = prm;
+  h->stream = (hipStream_t)stream;
+  h->last_ms = -1.0;
+  int wclk = 0;
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, h->device) != hipSuccess) {
+    delete h;
+    return MFIPM_ERR_HIP;
+  }
+  h->wall_khz = wclk > 0 ? wclk : 100000;
+  for (int op = 0; op < 2; ++op)
+    for (int bwd = 0; bwd < 2; ++bwd) {
+      int occ = 0;
+      const void* k = pick_kernel(op, bwd);
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds(op)) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, MF_THREADS, dyn_lds(op)) != hipSuccess) {
+        delete h;
+        return MFIPM_ERR_HIP;
+      }
+      h->occ[op][bwd] = occ;  // 0: this kernel cannot be resident; calls that need it fail
+    }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    delete h;
+    return MFIPM_ERR_HIP;
+  }
+  *hp = h;
+  return MFIPM_OK;
+}
+
+int mfipm_set_params(mfipm_handle* h, const mfipm_params* p) {
+  if (!h || check_params(p)) return MFIPM_ERR_INVALID_ARG;
+  h->prm = *p;
+  return MFIPM_OK;
+}
+
+int mfipm_destroy(mfipm_handle* h) {
+  if (!h) return MFIPM_OK;
+  (void)hipEventDestroy(h->ev0);
+  (void)hipEventDestroy(h->ev1);
+  delete h;
+  return MFIPM_OK;
+}
+
+int mfipm_set_launch(mfipm_handle* h, int32_t workgroups, int32_t team_size, int32_t tile_param) {
+  if (!h || workgroups < 0 || team_size < 0 || tile_param < 0) return MFIPM_ERR_INVALID_ARG;
+  h->req_wg = workgroups;
+  h->req_team = team_size;
+  h->req_tile = tile_param;
+  return MFIPM_OK;
+}
+
+double mfipm_last_kernel_ms(const mfipm_handle* h) { return h ? h->last_ms : -1.0; }
+
+int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, int64_t max_m, int32_t batch,
+                         size_t* bytes) {
+  if (!h || !bytes || batch < 1 || max_n < 1 || max_m < 1) return MFIPM_ERR_INVALID_ARG;
+  if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
+  size_t best = 0;
+  for (int bwd = 0; bwd < 2; ++bwd) {
+    const TeamLayout tl = team_layout(op_kind, max_n, max_m);
+    const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch), tl);
+    best = std::max(best, gl.total);
+  }
+  *bytes = best;
+  return MFIPM_OK;
+}
+
+int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau, double* x,
+                double* state, void* ws, size_t ws_bytes, mfipm_info* info) {
+  if (!h || !op) return MFIPM_ERR_INVALID_ARG;
+  if (op->op == MFIPM_OP_DENSE && op->lda != op->n) return MFIPM_ERR_INVALID_ARG;
+  const int64_t n_off[2] = {0, op->n}, m_off[2] = {0, op->m}, a_off[2] = {0, op->m * op->n};
+  Problem P{1, op->op, 1, n_off, m_off, a_off, &tau, op->n, op->m};
+  return launch(h, P, 0, op->A, op->rows, b, x, state, nullptr, nullptr, nullptr, ws, ws_bytes, info);
+}
+
+int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
+                        const int64_t* a_off, int32_t op_kind, const double* A_packed, const int32_t* rows_packed,
+                        int32_t shared_op, const double* b_packed, const double* tau, double* x_packed,
+                        double* state_packed, void* ws, size_t ws_bytes, mfipm_info* infos) {
+  if (!h || !n_off || !m_off || !tau || batch < 1) return MFIPM_ERR_INVALID_ARG;
+  long long nmax = 0, mmax = 0;
+  for (int i = 0; i < batch; ++i) {
+    nmax = std::max<long long>(nmax, n_off[i + 1] - n_off[i]);
+    mmax = std::max<long long>(mmax, m_off[i + 1] - m_off[i]);
+  }
+  Problem P{batch, op_kind, shared_op ? 1 : 0, n_off, m_off, a_off, tau, nmax, mmax};
+  return launch(h, P, 0, A_packed, rows_packed, b_packed, x_packed, state_packed, nullptr, nullptr, nullptr, ws,
+                ws_bytes, infos);
+}
+
+int mfipm_backward(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
+                   const int64_t* a_off, int32_t op_kind, const double* A_packed, const int32_t* rows_packed,
+                   int32_t shared_op, const double* state_packed, const double* grad_x_packed,
+                   double* grad_b_packed, double* grad_tau, void* ws, size_t ws_bytes, mfipm_info* infos) {
+  if (!h || !n_off || !m_off || batch < 1) return MFIPM_ERR_INVALID_ARG;
+  if (!state_packed) return MFIPM_ERR_NO_STATE;
+  long long nmax = 0, mmax = 0;
+  for (int i = 0; i < batch; ++i) {
+    nmax = std::max<long long>(nmax, n_off[i + 1] - n_off[i]);
+    mmax = std::max<long long>(mmax, m_off[i + 1] - m_off[i]);
+  }
+  Problem P{batch, op_kind, shared_op ? 1 : 0, n_off, m_off, a_off, nullptr, nmax, mmax};
+  return launch(h, P, 1, A_packed, rows_packed, nullptr, nullptr, const_cast<double*>(state_packed),
+                grad_x_packed, grad_b_packed, grad_tau, ws, ws_bytes, infos);
+}
+
+const char* mfipm_status_string(int32_t code) {
+  switch (code) {
+    case MFIPM_ERR_INVALID_ARG: return "invalid argument";
+    case MFIPM_ERR_HIP: return "HIP runtime error";
+    case MFIPM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case MFIPM_ERR_NO_STATE: return "no state from a forward solve";
+    case MFIPM_ERR_DEVICE_CHECK: return "device-side input check failed";
+    case MFIPM_STATUS_CONVERGED: return "converged";
+    case MFIPM_STATUS_MAXITER: return "iteration limit";
+    case MFIPM_STATUS_PCG_BREAKDOWN: return "PCG breakdown";
+    case MFIPM_STATUS_NONFINITE: return "non-finite value";
+    case MFIPM_STATUS_STEP_UNDERFLOW: return "step underflow";
+    case MFIPM_STATUS_ABORTED: return "aborted (device wait bound exceeded)";
+    case MFIPM_STATUS_INPUT_CHECK: return "input check failed";
+    default: return "unknown";
+  }
+}
+
+}  // extern "C"

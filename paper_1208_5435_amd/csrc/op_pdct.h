@@ -1,0 +1,407 @@
+// Partial DCT operator A = R_m C (C = orthonormal DCT-II of length n, R_m keeps
+// m sampled rows): the product K d = A^T A d = C^T M C d (M = 0/1 mask of the
+// kept coefficients) and the residual A^T (A x - b) = C^T (M C x - b~), where
+// b~ is b scattered to the kept coefficients.  Orthonormal rows (A A^T = I)
+// are the property the paper's preconditioner relies on (Section 3,
+// eq. (eq:orthonormality); Section 5, eq. (eq:ne2_P) with rho = m/n).
+//
+// Transform path (radix-2 FFT staged in LDS; Makhoul's DCT-via-FFT reordering
+// and the half-length complex FFT of a real sequence):
+//   gather    w_j = d_{4j} + i d_{4j+2},  w_{H-1-j} = d_{4j+3} + i d_{4j+1}
+//             (j < n/4, H = n/2), i.e. the even-then-reversed-odd reordering
+//             packed two reals per complex;
+//   FFT_H     four-step: column FFTs of length N1, twiddle exp(-2 pi i j2 k1/H),
+//             row FFTs of length N2 (H = N1 N2);
+//   spectral  per pair (k, H-k): split the real-FFT halves, rotate by
+//             exp(-i pi k/(2n)), scale -> DCT coefficients X_k, X_{n-k};
+//             apply mask / subtract b~; rebuild the Hermitian half-spectrum of
+//             the DCT-III input; pack for the inverse half-length FFT;
+//   IFFT_H    row inverse FFTs, conjugate twiddle, column inverse FFTs;
+//   scatter   the inverse of the gather gives t = C^T (...).
+// Passes: A = gather + column FFT (items: pairs of mirrored 4-column blocks),
+// B = row FFT + spectral + row IFFT (items: pairs of rows k1, N1-k1),
+// C = column IFFT + scatter (items as A).  Complex intermediates live in HBM
+// in item-major tiles so that both sides of each exchange are contiguous.
+#pragma once
+#include "common.h"
+
+#define PD_TILE_CPLX 4096  // LDS tile: 4096 complex doubles = 64 KiB
+#define PD_EPT (PD_TILE_CPLX / MF_THREADS)  // tile elements per thread
+
+// ------------------------------- radix kernels --------------------------------
+template <int R>
+__device__ __forceinline__ void dft_small(cplx (&v)[R], int sign);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(cplx (&v)[2], int) {
+  cplx a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(cplx (&v)[4], int sign) {
+  cplx a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+  cplx a2 = cadd(v[1], v[3]), a3 = cmul_si(csub(v[1], v[3]), sign);
+  v[0] = cadd(a0, a2);
+  v[2] = csub(a0, a2);
+  v[1] = cadd(a1, a3);
+  v[3] = csub(a1, a3);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<8>(cplx (&v)[8], int sign) {
+  cplx e[4] = {v[0], v[2], v[4], v[6]};
+  cplx o[4] = {v[1], v[3], v[5], v[7]};
+  dft_small<4>(e, sign);
+  dft_small<4>(o, sign);
+  const double h = 0.70710678118654752440;  // sqrt(2)/2
+  // o1 *= w8, o2 *= w8^2 = sign*i, o3 *= w8^3, with w8 = exp(sign*i*pi/4)
+  o[1] = cmul(o[1], mkc(h, sign * h));
+  o[2] = cmul_si(o[2], sign);
+  o[3] = cmul(o[3], mkc(-h, sign * h));
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    v[s] = cadd(e[s], o[s]);
+    v[s + 4] = csub(e[s], o[s]);
+  }
+}
+
+// One Stockham (self-sorting) radix-R pass over `count` independent
+// sequences of length L held in LDS, in place: every thread first loads all
+// its butterfly inputs to registers, the workgroup synchronises, then the
+// outputs are written.  Element (s, i) is at buf[s * sstride + i * istride].
+// log2M: log2 of the twiddle resolution of the instance (4 n).
+template <int R>
+__device__ void stockham_pass(cplx* buf, int L, int Ls, int count, int istride, int sstride, int sign,
+                              const Twiddle& tw, int log2M, int log2LsR) {
+  constexpr int NB = PD_EPT / R;
+  const int nbper = L / R;
+  const int nb = nbper * count;
+  cplx v[NB][R];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int bt = threadIdx.x + k * MF_THREADS;
+    if (bt < nb) {
+      int s, b;
+      if (istride == 1) {
+        s = bt / nbper;
+        b = bt - s * nbper;
+      } else {
+        s = bt % count;
+        b = bt / count;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = buf[s * sstride + (b + r * nbper) * istride];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const int bt = threadIdx.x + k * MF_THREADS;
+    if (bt < nb) {
+      int s, b;
+      if (istride == 1) {
+        s = bt / nbper;
+        b = bt - s * nbper;
+      } else {
+        s = bt % count;
+        b = bt / count;
+      }
+      const int j = b & (Ls - 1);
+      const int kk = b / Ls;
+      if (j != 0) {
+        // w1 = exp(sign * 2 pi i j / (Ls R)), powers by repeated products
+        const cplx w1 = tw.get((long)j << (log2M - log2LsR), sign);
+        cplx w = w1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[k][r] = cmul(v[k][r], w);
+          if (r + 1 < R) w = cmul(w, w1);
+        }
+      }
+      dft_small<R>(v[k], sign);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[s * sstride + (kk * Ls * R + j + r * Ls) * istride] = v[k][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Unnormalised DFT (sign -1) or inverse DFT (sign +1) of `count` sequences of
+// length L = 2^log2L (count * L <= 4096).  Caller synchronises before.
+__device__ inline void lds_fft(cplx* buf, int log2L, int count, int istride, int sstride, int sign,
+                               const Twiddle& tw, int log2M) {
+  const int L = 1 << log2L;
+  int Ls = 1, lg = 0;
+  while (Ls < L) {
+    const int rem = log2L - lg;
+    if (rem >= 3) {
+      stockham_pass<8>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 3);
+      Ls <<= 3;
+      lg += 3;
+    } else if (rem == 2) {
+      stockham_pass<4>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 2);
+      Ls <<= 2;
+      lg += 2;
+    } else {
+      stockham_pass<2>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 1);
+      Ls <<= 1;
+      lg += 1;
+    }
+  }
+}
+
+// pass-B modes
+enum { PB_HAPPLY = 0, PB_RESID = 1, PB_FWDOUT = 2 };
+
+struct OpPdct {
+  long n;
+  long m;
+  int H, N1, N2, l1, l2, logn;
+  const int* __restrict__ rows;
+  const double* __restrict__ b;
+  cplx* Y1;
+  cplx* Y2;
+  unsigned char* mask;  // spectral layout, n bytes
+  double* bt;           // spectral layout, n doubles
+  double* XS;           // spectral layout, n doubles (forward output)
+  Twiddle tw;
+  cplx* tile;  // LDS
+  double a0, a1;
+
+  __device__ int nA() const { return N2 >> 3; }
+  __device__ int nB() const { return N1 >> 1; }
+  __device__ int nC() const { return N2 >> 3; }
+  __device__ int log2M() const { return logn + 2; }
+
+  // position of coefficient-owner (half index k, e) in the spectral layout
+  __device__ __forceinline__ long spos(long k, int e) const {
+    return (((k & (N1 - 1)) * (long)N2 + (k >> l1)) << 1) + e;
+  }
+  // spectral-layout position of DCT coefficient index kk in [0, n)
+  __device__ __forceinline__ long coef_pos(long kk) const {
+    if (kk == 0) return spos(0, 0);
+    if (kk == H) return spos(0, 1);
+    if (kk < H) return spos(kk, 0);
+    return spos(n - kk, 1);
+  }
+
+  // Unit u in [0, 16 N1) of a column-block-pair item q -> d index and the
+  // tile slot (double offset into the LDS tile viewed as doubles).
+  __device__ __forceinline__ void unit_map(int q, int u, long& i, int& slot) const {
+    const int j1 = u >> 5, w = u & 31, seg = w >> 4, off = w & 15;
+    const int cc = off >> 2, e = off & 3;
+    const int j2 = seg == 0 ? 4 * q + cc : N2 - 4 - 4 * q + cc;
+    const int colA = seg == 0 ? cc : 4 + (3 - cc);
+    const int colM = seg == 0 ? 4 + cc : 3 - cc;
+    i = 4L * ((long)j1 * N2 + j2) + e;
+    if (e == 0) slot = (j1 * 8 + colA) * 2;
+    else if (e == 2) slot = (j1 * 8 + colA) * 2 + 1;
+    else if (e == 3) slot = ((N1 - 1 - j1) * 8 + colM) * 2;
+    else slot = ((N1 - 1 - j1) * 8 + colM) * 2 + 1;
+  }
+
+  // ---- pass A: gather d (from the functor) + column FFTs + twiddle -> Y1 ----
+  template <class F>
+  __device__ void passA(int q, F& f) {
+    double* td = reinterpret_cast<double*>(tile);
+    const int units = 16 * N1;
+    constexpr int U = 2;
+    for (int base = 0; base < units; base += MF_THREADS * U) {
+      typename F::In in[U];
+      long idx[U];
+      int slot[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int u = base + threadIdx.x + k * MF_THREADS;
+        if (u < units) {
+          unit_map(q, u, idx[k], slot[k]);
+          f.load(idx[k], in[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int u = base + threadIdx.x + k * MF_THREADS;
+        if (u < units) td[slot[k]] = f.gather(idx[k], in[k]);
+      }
+    }
+    __syncthreads();
+    lds_fft(tile, l1, 8, 8, 1, -1, tw, log2M());
+    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) {
+      const int k1 = e >> 3, c = e & 7;
+      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+      cplx v = tile[e];
+      v = cmul(v, tw.get(8L * ((long)j2 * k1), -1));
+      Y1[(long)q * N1 * 8 + e] = v;
+    }
+    __syncthreads();
+  }
+
+  // ---- pass C: Y2 -> column IFFTs -> scatter t to the functor ----
+  template <class F>
+  __device__ void passC(int q, F& f) {
+    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(long)q * N1 * 8 + e];
+    __syncthreads();
+    lds_fft(tile, l1, 8, 8, 1, +1, tw, log2M());
+    const double* td = reinterpret_cast<const double*>(tile);
+    const int units = 16 * N1;
+    constexpr int U = 2;
+    for (int base = 0; base < units; base += MF_THREADS * U) {
+      typename F::In in[U];
+      long idx[U];
+      int slot[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int u = base + threadIdx.x + k * MF_THREADS;
+        if (u < units) {
+          unit_map(q, u, idx[k], slot[k]);
+          f.load(idx[k], in[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int u = base + threadIdx.x + k * MF_THREADS;
+        if (u < units) f.scatter(idx[k], td[slot[k]], in[k]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // Spectral work for one pair of half-spectrum indices (kA, kB = H - kA).
+  // acc[0] += sum of squared outputs, acc[1] += sum b~ * output.
+  __device__ void spectral_pair(int mode, long kA, int pA, long kB, int pB, double (&acc)[2]) {
+    const cplx WA = tile[pA];
+    const double h = 0.70710678118654752440;
+    if (kA == 0) {
+      // V_0 = Re W0 + Im W0, V_H = Re W0 - Im W0 (both real)
+      const double V0 = WA.x + WA.y, VH = WA.x - WA.y;
+      double X0 = a0 * V0, XH = a1 * VH * h;
+      const long p0 = spos(0, 0), p1 = spos(0, 1);
+      if (mode == PB_FWDOUT) {
+        XS[p0] = X0;
+        XS[p1] = XH;
+        return;
+      }
+      const double m0 = mask[p0], m1 = mask[p1];
+      double Y0 = m0 * X0, YH = m1 * XH;
+      if (mode == PB_RESID) {
+        const double b0 = bt[p0], b1 = bt[p1];
+        Y0 -= b0;
+        YH -= b1;
+        acc[1] += b0 * Y0 + b1 * YH;
+      }
+      acc[0] += Y0 * Y0 + YH * YH;
+      const double c0 = a0 * Y0, cH = a1 * YH;
+      const double H0 = c0, HH = cH * h;
+      tile[pA] = mkc(H0 + HH, H0 - HH);  // (H0 + HH) + i (H0 - HH)
+      return;
+    }
+    const cplx WB = tile[pB];
+    // real-FFT split: E = (WA + conj WB)/2, O = (WA - conj WB) / (2i)
+    const cplx E = cscale(cadd(WA, cconj(WB)), 0.5);
+    const cplx Dd = csub(WA, cconj(WB));
+    const cplx O = mkc(0.5 * Dd.y, -0.5 * Dd.x);
+    const cplx VA = cadd(E, cmul(tw.get(4 * kA), O));
+    const cplx UA = cmul(tw.get(kA), VA);
+    const cplx VB = cadd(cconj(E), cmul(tw.get(4 * kB), cconj(O)));
+    const cplx UB = cmul(tw.get(kB), VB);
+    // coefficients owned: e=0 -> X_k = a1 Re U, e=1 -> X_{n-k} = -a1 Im U
+    const long qa0 = spos(kA, 0), qa1 = qa0 + 1, qb0 = spos(kB, 0), qb1 = qb0 + 1;
+    double xa0 = a1 * UA.x, xa1 = -a1 * UA.y, xb0 = a1 * UB.x, xb1 = -a1 * UB.y;
+    const bool self = (kA == kB);
+    if (mode == PB_FWDOUT) {
+      XS[qa0] = xa0;
+      XS[qa1] = xa1;
+      if (!self) {
+        XS[qb0] = xb0;
+        XS[qb1] = xb1;
+      }
+      return;
+    }
+    double ya0 = mask[qa0] * xa0, ya1 = mask[qa1] * xa1;
+    double yb0 = 0, yb1 = 0;
+    if (!self) {
+      yb0 = mask[qb0] * xb0;
+      yb1 = mask[qb1] * xb1;
+    }
+    if (mode == PB_RESID) {
+      const double ba0 = bt[qa0], ba1 = bt[qa1];
+      ya0 -= ba0;
+      ya1 -= ba1;
+      acc[1] += ba0 * ya0 + ba1 * ya1;
+      if (!self) {
+        const double bb0 = bt[qb0], bb1 = bt[qb1];
+        yb0 -= bb0;
+        yb1 -= bb1;
+        acc[1] += bb0 * yb0 + bb1 * yb1;
+      }
+    }
+    acc[0] += ya0 * ya0 + ya1 * ya1;
+    if (!self) acc[0] += yb0 * yb0 + yb1 * yb1;
+    else {
+      yb0 = ya0;
+      yb1 = ya1;
+    }
+    // inverse: c = a1 Y; Hk = 1/2 exp(+i pi k/(2n)) (c_k - i c_{n-k})
+    const cplx HA = cscale(cmul(cconj(tw.get(kA)), mkc(a1 * ya0, -a1 * ya1)), 0.5);
+    const cplx HB = cscale(cmul(cconj(tw.get(kB)), mkc(a1 * yb0, -a1 * yb1)), 0.5);
+    // G_k = (H_k + conj H_{H-k}) + i exp(2 pi i k/n) (H_k - conj H_{H-k})
+    const cplx GA = cadd(cadd(HA, cconj(HB)), cmul_si(cmul(cconj(tw.get(4 * kA)), csub(HA, cconj(HB))), 1));
+    tile[pA] = GA;
+    if (!self) {
+      const cplx GB =
+          cadd(cadd(HB, cconj(HA)), cmul_si(cmul(cconj(tw.get(4 * kB)), csub(HB, cconj(HA))), 1));
+      tile[pB] = GB;
+    }
+  }
+
+  // ---- pass B: two rows of Y1 -> row FFT -> spectral -> row IFFT -> Y2 ----
+  __device__ void passB(int r, int mode, double (&acc)[2]) {
+    const int k1a = r == 0 ? 0 : r;
+    const int k1b = r == 0 ? (N1 >> 1) : N1 - r;
+    for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
+      const int s = u2 >= N2;
+      const int u = u2 - s * N2;
+      const int q = u >> 3, c = u & 7;
+      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+      const int k1 = s ? k1b : k1a;
+      tile[s * N2 + j2] = Y1[((long)q * N1 + k1) * 8 + c];
+    }
+    __syncthreads();
+    lds_fft(tile, l2, 2, 1, N2, -1, tw, log2M());
+    if (r != 0) {
+      for (int u = threadIdx.x; u < N2; u += MF_THREADS) {
+        const long kA = k1a + (long)N1 * u;
+        const long kB = k1b + (long)N1 * (N2 - 1 - u);
+        spectral_pair(mode, kA, u, kB, N2 + (N2 - 1 - u), acc);
+      }
+    } else {
+      for (int u = threadIdx.x; u < N2 + 1; u += MF_THREADS) {
+        if (u <= (N2 >> 1)) {
+          const int pb = (N2 - u) & (N2 - 1);
+          spectral_pair(mode, (long)N1 * u, u, (long)N1 * pb, pb, acc);
+        } else {
+          const int v = u - (N2 >> 1) - 1;
+          const long kA = (N1 >> 1) + (long)N1 * v;
+          const long kB = (N1 >> 1) + (long)N1 * (N2 - 1 - v);
+          spectral_pair(mode, kA, N2 + v, kB, N2 + (N2 - 1 - v), acc);
+        }
+      }
+    }
+    __syncthreads();
+    if (mode == PB_FWDOUT) return;
+    lds_fft(tile, l2, 2, 1, N2, +1, tw, log2M());
+    for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
+      const int s = u2 >= N2;
+      const int u = u2 - s * N2;
+      const int q = u >> 3, c = u & 7;
+      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+      const int k1 = s ? k1b : k1a;
+      cplx v = tile[s * N2 + j2];
+      v = cmul(v, tw.get(8L * ((long)j2 * k1), +1));
+      Y2[((long)q * N1 + k1) * 8 + c] = v;
+    }
+    __syncthreads();
+  }
+};
