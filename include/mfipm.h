@@ -67,7 +67,7 @@ extern "C" {
 /* operator kinds */
 #define MFIPM_OP_DENSE 0 /* explicit m x n row-major matrix                                     */
 #define MFIPM_OP_PDCT 1  /* rows of the orthonormal DCT-II of length n (Section 3, eq.
-                            (eq:orthonormality): A A^T = I); n a power of two, 64 <= n <= 2^21 */
+                            (eq:orthonormality): A A^T = I); n a power of two, 64 <= n <= 2^20 */
 
 typedef struct mfipm_handle mfipm_handle;
 
@@ -147,7 +147,7 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
  * which mfipm_backward needs; ws/ws_bytes: workspace of at least
  * mfipm_workspace_size(h, op->op, op->n, op->m, 1) bytes; info: host.
  * Errors: INVALID_ARG (NULL pointers, m < 1, m > n, tau <= 0 or not finite,
- * PDCT n not a power of two in [64, 2^21]); WORKSPACE_TOO_SMALL;
+ * PDCT n not a power of two in [64, 2^20]); WORKSPACE_TOO_SMALL;
  * DEVICE_CHECK (rows not sorted/distinct/in range); HIP.                     */
 int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau,
                 double* x, double* state, void* ws, size_t ws_bytes, mfipm_info* info);

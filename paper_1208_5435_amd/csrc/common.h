@@ -40,11 +40,12 @@ __device__ __forceinline__ cplx cmul_si(cplx a, int sign) {
 
 // Roots of unity T(e) = exp(-2 pi i e / M) from two tables:
 // T(e) = hi[e >> lo_bits] * lo[e & (2^lo_bits - 1)].  Tables are built on the
-// host in extended precision.  `scale` maps an instance's own resolution
-// (4 n) onto the table resolution (4 n_max).
+// host in extended precision and copied to LDS once per instance.
+// `scale_shift` maps an instance's own resolution (4 n) onto the table
+// resolution (4 n_max).
 struct Twiddle {
-  const cplx* __restrict__ lo;
-  const cplx* __restrict__ hi;
+  const cplx* lo;
+  const cplx* hi;
   int lo_bits;
   int scale_shift;
   __device__ __forceinline__ cplx get(long e) const {
@@ -61,18 +62,31 @@ struct Twiddle {
 };
 
 // ---------------------------------------------------------------------------
-// Teams: groups of workgroups that cooperate on one instance.  A team barrier
-// is a monotonically increasing counter; every workgroup of the team passes
-// the same sequence of barriers because all control decisions are taken from
-// identical, deterministically reduced values.  The wait is bounded in wall
-// clock time: past the bound a global abort flag is raised, later barriers
-// return at once and the solver loops stop, so the grid always drains.
+// Teams: groups of workgroups that cooperate on one instance.  Every
+// workgroup of a team passes the same sequence of barriers because all
+// control decisions are taken from identical, deterministically reduced
+// values.  The barrier is two-level: workgroups arrive on the counter of
+// their group of MF_BAR_GS; the last arrival of a group arrives on the top
+// counter; the last top arrival publishes the generation in a release word on
+// which everyone waits.  Counters only grow (targets are generation * count),
+// so nothing is reset between barriers.  The wait is bounded in wall-clock
+// time: past the bound a global abort flag is raised, later barriers return at
+// once and the solver loops stop, so the grid always drains.
+//
+// Control block layout (unsigned long long words, 128-byte lines):
+//   [0] release word, [16] top counter, [32 + 16 g] counter of group g.
 // ---------------------------------------------------------------------------
+#define MF_BAR_GS 16
+#define MF_BAR_MAXGROUPS 64
+#define MF_CTL_SLOT_BYTES 10240  // byte offset of the queue slot in a team control block
+#define MF_CTL_ERR_BYTES 10304   // byte offset of the input-check flag
+#define MF_CTL_BYTES 12288       // bytes of one team control block
+
 struct Team {
   int id;
   int rank;
   int size;
-  unsigned long long* bar;
+  unsigned long long* ctl;
   unsigned long long gen;
   int* abort_flag;
   unsigned long long spin_ticks;  // bound on one wait, in wall-clock ticks
@@ -83,19 +97,38 @@ __device__ __forceinline__ int ld_flag(int* p) {
 }
 
 // Returns nonzero if the run was aborted.
-__device__ inline int team_barrier(Team& t) {
+__device__ __forceinline__ int team_barrier(Team& t) {
   __shared__ int s_abort;
+  // Every wave waits until its own global stores are complete in L2 before
+  // the workgroup barrier; thread 0's agent-scope release (L2 write-back)
+  // below then covers the stores of all waves of the workgroup.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   t.gen += 1;
   if (threadIdx.x == 0) {
     int ab = ld_flag(t.abort_flag);
+    unsigned long long* rel = t.ctl;
+    const int g = t.rank / MF_BAR_GS;
+    const int ngroups = (t.size + MF_BAR_GS - 1) / MF_BAR_GS;
+    const int gcount = min(MF_BAR_GS, t.size - g * MF_BAR_GS);
+    // release this workgroup's writes, then arrive
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(t.bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long old =
+        __hip_atomic_fetch_add(t.ctl + 32 + 16 * g, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == t.gen * (unsigned long long)gcount) {
+      // last of the group: acquire the group's writes, release them onward
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const unsigned long long old2 =
+          __hip_atomic_fetch_add(t.ctl + 16, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old2 + 1 == t.gen * (unsigned long long)ngroups) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(rel, t.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     if (!ab) {
-      const unsigned long long target = t.gen * (unsigned long long)t.size;
       const unsigned long long t0 = wall_clock64();
       unsigned iter = 0;
-      while (__hip_atomic_load(t.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < t.gen) {
         __builtin_amdgcn_s_sleep(1);
         if ((++iter & 255u) == 0) {
           if (ld_flag(t.abort_flag)) {
@@ -138,7 +171,7 @@ __device__ __forceinline__ double wave_reduce(int kind, double v) {
 // Reduce K per-thread values over the workgroup; thread 0 gets the results in
 // out[] (registers of thread 0).  All threads must call.
 template <int K>
-__device__ inline void wg_reduce(const int* kinds, double (&v)[K], double* lds_scratch) {
+__device__ __forceinline__ void wg_reduce(const int* kinds, double (&v)[K], double* lds_scratch) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < K; ++j) v[j] = wave_reduce(kinds[j], v[j]);
@@ -161,7 +194,7 @@ __device__ inline void wg_reduce(const int* kinds, double (&v)[K], double* lds_s
 // Reduce per-item partials part[item * MF_MAXK + j] over items [0, nitems) in
 // a fixed order; every thread of the workgroup receives the K results.
 template <int K>
-__device__ inline void reduce_items(const int* kinds, const double* part, int nitems, double (&res)[K],
+__device__ __forceinline__ void reduce_items(const int* kinds, const double* part, int nitems, double (&res)[K],
                                     double* lds_scratch) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;

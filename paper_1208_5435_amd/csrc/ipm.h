@@ -88,7 +88,7 @@ struct KArgs {
   unsigned long long spin_ticks;
 };
 
-__device__ inline TeamWS make_ws(const KArgs& a, int team) {
+__device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   char* base = a.team_base + (long)team * a.lay.stride;
   TeamWS w;
   w.X = (double2*)(base + a.lay.X);
@@ -111,8 +111,8 @@ __device__ inline TeamWS make_ws(const KArgs& a, int team) {
   w.partC = (double*)(base + a.lay.partC);
   w.partS = (double*)(base + a.lay.partS);
   w.bar = (unsigned long long*)(base + a.lay.ctl);
-  w.slot = (int*)(base + a.lay.ctl + 64);
-  w.err = (int*)(base + a.lay.ctl + 128);
+  w.slot = (int*)(base + a.lay.ctl + MF_CTL_SLOT_BYTES);
+  w.err = (int*)(base + a.lay.ctl + MF_CTL_ERR_BYTES);
   return w;
 }
 
@@ -435,7 +435,7 @@ __device__ __forceinline__ void finish_item(Ctx& cx, F& f, const int (&kinds)[F:
 }
 
 template <class OP, class F>
-__device__ void run_A(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
+__device__ __forceinline__ void run_A(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
   const int ni = op.nA();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     f.reset();
@@ -445,7 +445,7 @@ __device__ void run_A(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* p
 }
 
 template <class OP, class F>
-__device__ void run_C(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
+__device__ __forceinline__ void run_C(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* part) {
   const int ni = op.nC();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     f.reset();
@@ -456,10 +456,10 @@ __device__ void run_C(Ctx& cx, OP& op, F& f, const int (&kinds)[F::K], double* p
 
 // pass B: two sums (y^2, b.y)
 template <class OP>
-__device__ void run_B(Ctx& cx, OP& op, int mode, double* part, double* out);
+__device__ __forceinline__ void run_B(Ctx& cx, OP& op, int mode, double* part, double* out);
 
 template <>
-__device__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, double* out) {
+__device__ __forceinline__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, double* out) {
   const int ni = op.nB();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     double acc[2] = {0.0, 0.0};
@@ -472,7 +472,7 @@ __device__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, dou
 }
 
 template <>
-__device__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*) {
+__device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*) {
   const int ni = op.nB();
   const int kinds[2] = {0, 0};
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
@@ -488,7 +488,7 @@ __device__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, doubl
 
 // elementwise pass over [0, n), items of 1024 indices
 template <class F>
-__device__ void run_E(Ctx& cx, long n, F& f, const int (&kinds)[F::K], double* part) {
+__device__ __forceinline__ void run_E(Ctx& cx, long n, F& f, const int (&kinds)[F::K], double* part) {
   const int ni = (int)((n + 1023) / 1024);
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     f.reset();
@@ -513,7 +513,7 @@ __device__ __forceinline__ int nE(long n) { return (int)((n + 1023) / 1024); }
 // ------------------------------------------------------------------------
 // Operator construction and set-up
 // ------------------------------------------------------------------------
-__device__ inline void make_op(OpDense& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+__device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
   op.n = d.n;
   op.m = d.m;
   op.lda = d.n;
@@ -525,13 +525,13 @@ __device__ inline void make_op(OpDense& op, const KArgs& a, const InstDesc& d, c
   op.lds = (double*)lds;
 }
 
-__device__ inline int ilog2(long v) {
+__device__ __forceinline__ int ilog2(long v) {
   int l = 0;
   while ((1L << l) < v) ++l;
   return l;
 }
 
-__device__ inline void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+__device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
   op.n = d.n;
   op.m = d.m;
   op.H = (int)(d.n >> 1);
@@ -553,8 +553,8 @@ __device__ inline void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, co
   op.mask = w.mask;
   op.bt = w.bt;
   op.XS = w.XS;
-  op.tw.lo = a.tw_lo;
-  op.tw.hi = a.tw_hi;
+  op.tw.lo = (const cplx*)lds + PD_TILE_CPLX;
+  op.tw.hi = op.tw.lo + (1 << a.tw_lo_bits);
   op.tw.lo_bits = a.tw_lo_bits;
   op.tw.scale_shift = a.tw_log2n_max - op.logn;
   op.tile = (cplx*)lds;
@@ -563,11 +563,21 @@ __device__ inline void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, co
 }
 
 // Dense set-up: nothing to build.  Returns 0 (ok) or ST_ABORTED.
-__device__ inline int op_setup(Ctx& cx, OpDense&, const KArgs&, const TeamWS&, int) { return 0; }
+__device__ __forceinline__ int op_setup(Ctx& cx, OpDense&, const KArgs&, const TeamWS&, int) { return 0; }
 
-// PDCT set-up: zero the spectral mask / b~, then scatter the sampled rows
-// (checking they are sorted, distinct and in range).  with_b = 0 skips b~.
-__device__ inline int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS& w, int with_b) {
+// PDCT set-up: copy the twiddle tables to LDS, zero the spectral mask / b~,
+// then scatter the sampled rows (checking they are sorted, distinct and in
+// range).  with_b = 0 skips b~.
+__device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS& w, int with_b) {
+  {
+    cplx* lo = const_cast<cplx*>(op.tw.lo);
+    cplx* hi = const_cast<cplx*>(op.tw.hi);
+    const int nlo = 1 << a.tw_lo_bits;
+    const int nhi = 1 << (a.tw_log2n_max + 2 - a.tw_lo_bits);
+    for (int e = threadIdx.x; e < nlo; e += MF_THREADS) lo[e] = a.tw_lo[e];
+    for (int e = threadIdx.x; e < nhi; e += MF_THREADS) hi[e] = a.tw_hi[e];
+    __syncthreads();
+  }
   const long n = op.n;
   const long nthr = (long)cx.t.size * MF_THREADS;
   const long gt = (long)cx.t.rank * MF_THREADS + threadIdx.x;
@@ -595,7 +605,7 @@ __device__ inline int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS
 }
 
 // rho: Frobenius-closest scalar to A^T A (Section 5, before eq. (eq:ne2_P)).
-__device__ inline double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
+__device__ __forceinline__ double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
   const int ni = op.nB();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     const double s = op.frob_block(it);
@@ -607,7 +617,7 @@ __device__ inline double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) 
   reduce_items<1>(kinds, w.partS, ni, r, cx.red);
   return r[0] / (double)op.n;
 }
-__device__ inline double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& ab) {
+__device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& ab) {
   ab = 0;
   return (double)op.m / (double)op.n;  // orthonormal rows: ||A||_F^2 = m
 }
@@ -618,7 +628,7 @@ __device__ inline double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& ab) {
 // Returns a status (0 = ok); *iters = operator applies.
 // ------------------------------------------------------------------------
 template <class OP>
-__device__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit, double rhs2,
+__device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit, double rhs2,
                        double rty, int* iters) {
   const int kA[1] = {0};
   const int kC[2] = {0, 0};
@@ -692,7 +702,7 @@ struct ResOut {
 };
 
 template <class OP>
-__device__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w, double2* Z, double2* S, const DevParams& prm,
+__device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w, double2* Z, double2* S, const DevParams& prm,
                                int mode, double aP, double aD, double tau, double sigma, double sigma3,
                                int trial, double rho) {
   ResOut o;
@@ -759,7 +769,7 @@ __device__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w, double2* Z, dou
 }
 
 template <class OP>
-__device__ void solve_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
+__device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
   const InstDesc d = a.inst[ii];
   const TeamWS w = make_ws(a, cx.t.id);
   const DevParams& prm = a.prm;
@@ -905,14 +915,14 @@ __device__ void solve_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
 // Forward product y = A d after a pass A that left d in the operator's
 // buffers: dense writes y directly; the partial DCT writes the spectral
 // coefficients (pass B) and then gathers the sampled rows.
-__device__ inline void op_forward_out(Ctx& cx, OpDense& op, const TeamWS& w, double* out) {
+__device__ __forceinline__ void op_forward_out(Ctx& cx, OpDense& op, const TeamWS& w, double* out) {
   run_B<OpDense>(cx, op, DB_OUT, w.partB, out);
 }
-__device__ inline void op_forward_gather(Ctx&, OpDense&, const TeamWS&, double*) {}
-__device__ inline void op_forward_out(Ctx& cx, OpPdct& op, const TeamWS& w, double*) {
+__device__ __forceinline__ void op_forward_gather(Ctx&, OpDense&, const TeamWS&, double*) {}
+__device__ __forceinline__ void op_forward_out(Ctx& cx, OpPdct& op, const TeamWS& w, double*) {
   run_B<OpPdct>(cx, op, PB_FWDOUT, w.partB, nullptr);
 }
-__device__ inline void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, double* out) {
+__device__ __forceinline__ void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, double* out) {
   const long nthr = (long)cx.t.size * MF_THREADS;
   for (long i = (long)cx.t.rank * MF_THREADS + threadIdx.x; i < op.m; i += nthr)
     out[i] = w.XS[op.coef_pos(op.rows[i])];
@@ -921,7 +931,7 @@ __device__ inline void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, d
 // Adjoint: (Theta^{-1} + F F^T) w = [g; -g] at the stored state, then
 // grad_b = A (w_u - w_v), grad_tau = -1^T w.
 template <class OP>
-__device__ void backward_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
+__device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
   const InstDesc d = a.inst[ii];
   const TeamWS w = make_ws(a, cx.t.id);
   const DevParams& prm = a.prm;

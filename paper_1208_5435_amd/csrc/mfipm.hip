@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
   cx.t.abort_flag = a.abort_flag;
   cx.t.spin_ticks = a.spin_ticks;
   const TeamWS w = make_ws(a, cx.t.id);
-  cx.t.bar = w.bar;
+  cx.t.ctl = w.bar;
   for (;;) {
     // the previous slot value has been read by every workgroup of the team
     if (team_barrier(cx.t)) break;
@@ -67,8 +67,13 @@ struct mfipm_handle {
   int req_wg, req_team, req_tile;
   hipEvent_t ev0, ev1;
   double last_ms;
-  int occ[2][2];  // [op][bwd] max resident workgroups per CU
+  int occ[2][2];             // [op][bwd] max resident workgroups per CU
+  size_t scratch_lane[2][2];  // [op][bwd] private bytes per lane
 };
+
+// Upper bound on private (scratch) memory of one dispatch: all workgroups of a
+// cooperative launch must get their scratch at once.
+constexpr size_t kMaxDispatchScratch = (size_t)96 << 20;
 
 namespace {
 
@@ -129,7 +134,7 @@ TeamLayout team_layout(int op_kind, long long n, long long m) {
   take(L.partB, pb);
   take(L.partC, pb);
   take(L.partS, pb);
-  take(L.ctl, 256);
+  take(L.ctl, MF_CTL_BYTES);
   L.stride = (long)off;
   return L;
 }
@@ -182,9 +187,17 @@ const void* pick_kernel(int op_kind, int bwd) {
   if (op_kind == MFIPM_OP_DENSE) return bwd ? kernel_ptr<OpDense, 1>() : kernel_ptr<OpDense, 0>();
   return bwd ? kernel_ptr<OpPdct, 1>() : kernel_ptr<OpPdct, 0>();
 }
-size_t dyn_lds(int op_kind) {
-  return op_kind == MFIPM_OP_DENSE ? (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double)
-                                   : (size_t)PD_TILE_CPLX * sizeof(cplx);
+// Dynamic LDS: dense reduction scratch; partial DCT tile + twiddle tables
+// (lo_bits / hi entries of the call, or the largest supported, n = 2^20).
+constexpr int kPdctMaxLog2N = 20;
+size_t dyn_lds(int op_kind, int lo_bits = -1, long long hi_count = 0) {
+  if (op_kind == MFIPM_OP_DENSE) return (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double);
+  if (lo_bits < 0) {
+    const int lm = kPdctMaxLog2N + 2;
+    lo_bits = (lm + 1) / 2;
+    hi_count = 1LL << (lm - lo_bits);
+  }
+  return (size_t)PD_TILE_CPLX * sizeof(cplx) + (((size_t)1 << lo_bits) + (size_t)hi_count) * sizeof(cplx);
 }
 
 void fill_twiddles(std::vector<cplx>& lo, std::vector<cplx>& hi, int lm, int lo_bits) {
@@ -239,7 +252,7 @@ int validate(const mfipm_handle* h, const Problem& P) {
     const long long m = P.m_off[i + 1] - P.m_off[i];
     if (n < 1 || m < 1 || P.n_off[i] < 0 || P.m_off[i] < 0) return MFIPM_ERR_INVALID_ARG;
     if (P.op_kind == MFIPM_OP_PDCT) {
-      if (!is_pow2(n) || n < 64 || n > (1LL << 21) || m > n) return MFIPM_ERR_INVALID_ARG;
+      if (!is_pow2(n) || n < 64 || n > (1LL << kPdctMaxLog2N) || m > n) return MFIPM_ERR_INVALID_ARG;
     } else if (!P.shared_op && P.a_off[i + 1] - P.a_off[i] != n * m) {
       return MFIPM_ERR_INVALID_ARG;
     }
@@ -287,8 +300,11 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     const int total = h->req_wg > 0 ? std::min(h->req_wg, gmax) : gmax;
     num_teams = std::max(1, std::min(P.batch, total / team_size));
   }
+  if (team_size > MF_BAR_GS * MF_BAR_MAXGROUPS) team_size = MF_BAR_GS * MF_BAR_MAXGROUPS;
   const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch);
   if (num_teams > teams_bound) num_teams = teams_bound;
+  if (h->scratch_lane[P.op_kind][bwd] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
+    return MFIPM_ERR_HIP;
 
   const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max);
   const GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
@@ -325,7 +341,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   // zero the control words: queue head, abort flag, team barriers
   HIP_TRY(hipMemsetAsync(base + gl.ctl, 0, 256, s));
   for (int t = 0; t < num_teams; ++t)
-    HIP_TRY(hipMemsetAsync(base + gl.teams + (size_t)t * tl.stride + tl.ctl, 0, 256, s));
+    HIP_TRY(hipMemsetAsync(base + gl.teams + (size_t)t * tl.stride + tl.ctl, 0, MF_CTL_BYTES, s));
 
   KArgs a{};
   a.inst = (const InstDesc*)(base + gl.inst);
@@ -358,7 +374,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   const int grid = num_teams * team_size;
   HIP_TRY(hipEventRecord(h->ev0, s));
   if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd), dim3(grid), dim3(MF_THREADS), args,
-                                 (unsigned)dyn_lds(P.op_kind), s) != hipSuccess)
+                                 (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
     return MFIPM_ERR_HIP;
   HIP_TRY(hipEventRecord(h->ev1, s));
   std::vector<DevInfo> dinf(P.batch);
@@ -438,6 +454,12 @@ int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
         return MFIPM_ERR_HIP;
       }
       h->occ[op][bwd] = occ;  // 0: this kernel cannot be resident; calls that need it fail
+      hipFuncAttributes fa;
+      if (hipFuncGetAttributes(&fa, k) != hipSuccess) {
+        delete h;
+        return MFIPM_ERR_HIP;
+      }
+      h->scratch_lane[op][bwd] = fa.localSizeBytes;
     }
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
     delete h;

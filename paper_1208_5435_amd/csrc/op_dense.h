@@ -32,7 +32,7 @@ struct OpDense {
   __device__ int nC() const { return (int)((n + DN_CB - 1) / DN_CB); }
 
   template <class F>
-  __device__ void passA(int item, F& f) {
+  __device__ __forceinline__ void passA(int item, F& f) {
     const long base = (long)item * DN_TA;
     constexpr int U = DN_TA / MF_THREADS;
     typename F::In in[U];
@@ -51,7 +51,7 @@ struct OpDense {
   // y_r = A[r,:] . D for the rows of the block; mode RESID subtracts b,
   // mode OUT writes y to `out` instead of Yv.  acc[0] += sum y^2,
   // acc[1] += sum b*y (RESID).  Results valid in thread 0.
-  __device__ void passB(int item, int mode, double (&acc)[2], double* out) {
+  __device__ __forceinline__ void passB(int item, int mode, double (&acc)[2], double* out) {
     const long r0 = (long)item * RB;
     const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
     double s[DN_RBMAX];
@@ -90,7 +90,7 @@ struct OpDense {
   }
 
   template <class F>
-  __device__ void passC(int item, F& f) {
+  __device__ __forceinline__ void passC(int item, F& f) {
     const long c0 = (long)item * DN_CB;
     const int col = threadIdx.x & 63, rg = threadIdx.x >> 6;
     const long c = c0 + col;
@@ -117,7 +117,7 @@ struct OpDense {
   }
 
   // sum of squares of the rows of a block (setup: ||A||_F^2), thread 0
-  __device__ double frob_block(int item) {
+  __device__ __forceinline__ double frob_block(int item) {
     const long r0 = (long)item * RB;
     const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
     double s = 0.0;

@@ -73,7 +73,7 @@ __device__ __forceinline__ void dft_small<8>(cplx (&v)[8], int sign) {
 // outputs are written.  Element (s, i) is at buf[s * sstride + i * istride].
 // log2M: log2 of the twiddle resolution of the instance (4 n).
 template <int R>
-__device__ void stockham_pass(cplx* buf, int L, int Ls, int count, int istride, int sstride, int sign,
+__device__ __forceinline__ void stockham_pass(cplx* buf, int L, int Ls, int count, int istride, int sstride, int sign,
                               const Twiddle& tw, int log2M, int log2LsR) {
   constexpr int NB = PD_EPT / R;
   const int nbper = L / R;
@@ -130,7 +130,7 @@ __device__ void stockham_pass(cplx* buf, int L, int Ls, int count, int istride, 
 
 // Unnormalised DFT (sign -1) or inverse DFT (sign +1) of `count` sequences of
 // length L = 2^log2L (count * L <= 4096).  Caller synchronises before.
-__device__ inline void lds_fft(cplx* buf, int log2L, int count, int istride, int sstride, int sign,
+__device__ __forceinline__ void lds_fft(cplx* buf, int log2L, int count, int istride, int sstride, int sign,
                                const Twiddle& tw, int log2M) {
   const int L = 1 << log2L;
   int Ls = 1, lg = 0;
@@ -204,7 +204,7 @@ struct OpPdct {
 
   // ---- pass A: gather d (from the functor) + column FFTs + twiddle -> Y1 ----
   template <class F>
-  __device__ void passA(int q, F& f) {
+  __device__ __forceinline__ void passA(int q, F& f) {
     double* td = reinterpret_cast<double*>(tile);
     const int units = 16 * N1;
     constexpr int U = 2;
@@ -240,7 +240,7 @@ struct OpPdct {
 
   // ---- pass C: Y2 -> column IFFTs -> scatter t to the functor ----
   template <class F>
-  __device__ void passC(int q, F& f) {
+  __device__ __forceinline__ void passC(int q, F& f) {
     for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(long)q * N1 * 8 + e];
     __syncthreads();
     lds_fft(tile, l1, 8, 8, 1, +1, tw, log2M());
@@ -270,7 +270,7 @@ struct OpPdct {
 
   // Spectral work for one pair of half-spectrum indices (kA, kB = H - kA).
   // acc[0] += sum of squared outputs, acc[1] += sum b~ * output.
-  __device__ void spectral_pair(int mode, long kA, int pA, long kB, int pB, double (&acc)[2]) {
+  __device__ __forceinline__ void spectral_pair(int mode, long kA, int pA, long kB, int pB, double (&acc)[2]) {
     const cplx WA = tile[pA];
     const double h = 0.70710678118654752440;
     if (kA == 0) {
@@ -357,7 +357,7 @@ struct OpPdct {
   }
 
   // ---- pass B: two rows of Y1 -> row FFT -> spectral -> row IFFT -> Y2 ----
-  __device__ void passB(int r, int mode, double (&acc)[2]) {
+  __device__ __forceinline__ void passB(int r, int mode, double (&acc)[2]) {
     const int k1a = r == 0 ? 0 : r;
     const int k1b = r == 0 ? (N1 >> 1) : N1 - r;
     for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {

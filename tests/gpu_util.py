@@ -26,8 +26,16 @@ def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label
     if np.max(np.abs(ref.x)) <= 1e-8 * (1 + np.max(np.abs(b))):
         # degenerate x* = 0: absolute gate
         assert np.max(np.abs(xg)) <= 1e-8 * (1 + np.max(np.abs(b))), label
-    else:
-        assert rel(xg, ref.x) <= X_REL, (label, rel(xg, ref.x))
+    elif rel(xg, ref.x) > X_REL:
+        # The gap test only fixes x to O(gap): when the objective is tiny the
+        # tolerance leaves x loose.  Then both answers are compared with a
+        # tightly converged oracle solution; the GPU's may be no farther from
+        # it than twice the oracle's own distance (plus the bar).
+        tight = R.solve(op, b, tau, R.Params(tol=1e-12, tolpcg=1e-8, mxiterpcg=2000))
+        d_ref = rel(ref.x, tight.x)
+        d_gpu = rel(xg, tight.x)
+        assert d_ref > X_REL / 10, (label, "tolerance determines x, yet GPU differs", rel(xg, ref.x))
+        assert d_gpu <= 2 * d_ref + X_REL, (label, d_gpu, d_ref)
     if ref.status == R.CONVERGED:
         if state is not None:
             n = op.n
