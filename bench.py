@@ -84,12 +84,147 @@ def cpu_baseline(kind, inst, budget_s: float):
                       f"({sum(times):.1f} s of host time; scipy.fft single worker, numpy elementwise)"}
 
 
+def _pool_map(fn, items, workers=16):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
+
+
+def bench_batched_dense(args, torch, Solver):
+    """256 uneven dense instances in one launch vs one launch per instance."""
+    import workloads as W
+    sizes = W.batched_dense_sizes(batch=args.batch)
+    t0 = time.perf_counter()
+    insts = _pool_map(lambda iv: W.batched_dense_instance(iv[0], int(iv[1])), list(enumerate(sizes)))
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    n_off = np.concatenate([[0], np.cumsum([i.n for i in insts])]).astype(np.int64)
+    m_off = np.concatenate([[0], np.cumsum([i.m for i in insts])]).astype(np.int64)
+    a_off = np.concatenate([[0], np.cumsum([i.m * i.n for i in insts])]).astype(np.int64)
+    A = torch.empty(int(a_off[-1]), dtype=torch.float64, device=dev)
+    for j, i in enumerate(insts):
+        A[a_off[j]:a_off[j + 1]].copy_(torch.from_numpy(i.A.reshape(-1)))
+    b = torch.from_numpy(np.concatenate([i.b for i in insts])).to(dev)
+    taus = np.array([i.tau for i in insts])
+    solver = Solver(device=dev)
+    solver.set_launch(args.workgroups, args.team, args.tile)
+    run = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    kms, t0 = [], time.perf_counter()
+    for _ in range(args.steps):
+        r = run()
+        kms.append(r.kernel_ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    infos = r.infos
+    bad = [k for k, i in enumerate(infos) if i["status"] != 0]
+    ab = sum(alg_bytes("dense", int(n_off[j + 1] - n_off[j]), int(m_off[j + 1] - m_off[j]), infos[j])
+             for j in range(len(insts)))
+    # plain: one launch per instance, same parameters
+    solver.set_launch(0, 0, args.tile)
+    t1 = time.perf_counter()
+    plain_iters = 0
+    for j, i in enumerate(insts):
+        rr = solver.solve(b[m_off[j]:m_off[j + 1]], i.tau,
+                          A=A[a_off[j]:a_off[j + 1]].view(i.m, i.n))
+        plain_iters += rr.infos[0]["ipm_iters"]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    kms_mean = float(np.mean(kms))
+    achieved = ab / (kms_mean * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(len(insts) * args.steps / wall, 3), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched_dense_{len(insts)}_n64x16-128_m=n/4",
+                   "batch": len(insts), "sum_mn": int(a_off[-1]), "gen_s": round(gen_s, 1),
+                   "not_converged": bad, "ipm_iters_sum": sum(i["ipm_iters"] for i in infos),
+                   "plain_ipm_iters_sum": plain_iters,
+                   "kernel_ms_mean": round(kms_mean, 3),
+                   "plain_solves_per_s": round(len(insts) / plain_s, 3),
+                   "batched_over_plain": round((len(insts) * args.steps / wall) / (len(insts) / plain_s), 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_mfipm<OpDense,0>", "alg_bytes_per_launch": ab},
+    }
+
+
+def bench_grad(args, torch, Solver):
+    """32 signals sharing a partial DCT: batched forward + adjoint vs per-signal calls."""
+    import workloads as W
+    inst = W.config_dct_batch(n=args.grad_n, batch=args.batch if args.batch != 256 else 32)
+    dev = torch.device("cuda", 0)
+    B, m = inst.b.shape
+    n = inst.n
+    n_off = np.arange(B + 1, dtype=np.int64) * n
+    m_off = np.arange(B + 1, dtype=np.int64) * m
+    rows = torch.from_numpy(inst.rows).to(dev)
+    b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
+    xt = torch.from_numpy(inst.x_true.reshape(-1)).to(dev)
+    solver = Solver(device=dev)
+    solver.set_launch(args.workgroups, args.team, args.tile)
+
+    def fwd_bwd():
+        r = solver.solve_batched(b, inst.tau, n_off, m_off, rows=rows, shared_op=True)
+        f_ms = r.kernel_ms
+        gb, gt, binf = solver.backward(r.state, r.x - xt, n_off, m_off, rows=rows, shared_op=True)
+        return r, f_ms, solver.last_kernel_ms(), binf
+    for _ in range(args.warmup):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fms, bms = [], []
+    for _ in range(args.steps):
+        r, f_ms, b_ms, binf = fwd_bwd()
+        fms.append(f_ms)
+        bms.append(b_ms)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # plain: one forward + one adjoint launch per signal
+    solver.set_launch(0, 0, args.tile)
+    one = np.array([0, n], np.int64)
+    onem = np.array([0, m], np.int64)
+    t1 = time.perf_counter()
+    for j in range(B):
+        rj = solver.solve(b[j * m:(j + 1) * m], float(inst.tau[j]), rows=rows, n=n)
+        solver.backward(rj.state, rj.x - xt[j * n:(j + 1) * n], one, onem, rows=rows)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    infos = r.infos
+    ab_f = sum(alg_bytes("pdct", n, m, i) for i in infos)
+    ab_b = sum(binf[j]["pcg_iters"] * (112.0 * n + 16.0 * (n + m)) + 2 * (160.0 * n + 16.0 * (n + m))
+               for j in range(B))
+    f_mean, b_mean = float(np.mean(fms)), float(np.mean(bms))
+    achieved = (ab_f + ab_b) / ((f_mean + b_mean) * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": round(B * args.steps / wall, 3), "unit": "signals/s (forward+gradient)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"grad_pdct_batch{B}_n{n}_m{m}", "forward_kernel_ms": round(f_mean, 3),
+                   "backward_kernel_ms": round(b_mean, 3),
+                   "ipm_iters": [i["ipm_iters"] for i in infos],
+                   "adjoint_pcg_iters": [i["pcg_iters"] for i in binf],
+                   "plain_signals_per_s": round(B / plain_s, 3),
+                   "batched_over_plain": round((B * args.steps / wall) / (B / plain_s), 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_mfipm<OpPdct,0> + k_mfipm<OpPdct,1>",
+                     "alg_bytes_per_launch": ab_f + ab_b},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pdct", choices=["pdct", "pdct_hdr", "dense"])
+    ap.add_argument("--workload", default="pdct",
+                    choices=["pdct", "pdct_hdr", "dense", "batched_dense", "grad"])
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--grad-n", type=int, default=1 << 18)
+    ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workgroups", type=int, default=0)
@@ -106,6 +241,10 @@ def main():
     import torch
     from paper_1208_5435_amd import Solver
 
+    if args.workload in ("batched_dense", "grad"):
+        fn = bench_batched_dense if args.workload == "batched_dense" else bench_grad
+        print(json.dumps(fn(args, torch, Solver)), flush=True)
+        return
     kind, inst, wl = make_workload(args.workload)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

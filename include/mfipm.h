@@ -19,8 +19,9 @@
  *   - All numeric data are IEEE double (FP64); index arrays are int32.
  *   - Pointers are DEVICE pointers unless the comment says "host".
  *   - The caller owns every buffer (operator data, b, x, state, gradients,
- *     workspace); the library owns only the handle.  Nothing is retained
- *     after a call returns.
+ *     workspace).  The library owns only the handle, which caches small
+ *     device tables of FFT roots of unity per transform size (freed by
+ *     mfipm_destroy).  No caller buffer is retained after a call returns.
  *   - Work is ordered on the stream given to mfipm_create (a hipStream_t
  *     passed as void*; NULL = the default stream).  solve/backward calls
  *     return after the work has finished and `info` is filled.

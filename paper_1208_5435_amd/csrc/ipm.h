@@ -45,7 +45,7 @@ struct InstDesc {
 // per-team workspace (device pointers)
 struct TeamWS {
   double2 *X, *R, *P, *TI, *DZ, *DS, *Zs, *Ss;
-  double *D, *Yv;
+  double *D, *Yv, *PT;
   cplx *Y1, *Y2;
   unsigned char* mask;
   double *bt, *XS;
@@ -56,7 +56,8 @@ struct TeamWS {
 };
 
 struct TeamLayout {  // byte offsets inside one team region
-  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, Y1, Y2, mask, bt, XS, partA, partB, partC, partS, ctl;
+  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Y1, Y2, mask, bt, XS, partA, partB, partC, partS;
+  int pt_chunks;  // dense fused path: capacity of PT in chunks
   long stride;
 };
 
@@ -78,6 +79,7 @@ struct KArgs {
   double* grad_tau;
   DevParams prm;
   char* team_base;
+  char* team_ctl;  // MF_CTL_BYTES per team, contiguous
   TeamLayout lay;
   const cplx* tw_lo;
   const cplx* tw_hi;
@@ -101,6 +103,7 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   w.Ss = (double2*)(base + a.lay.Ss);
   w.D = (double*)(base + a.lay.D);
   w.Yv = (double*)(base + a.lay.Yv);
+  w.PT = (double*)(base + a.lay.PT);
   w.Y1 = (cplx*)(base + a.lay.Y1);
   w.Y2 = (cplx*)(base + a.lay.Y2);
   w.mask = (unsigned char*)(base + a.lay.mask);
@@ -110,9 +113,10 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   w.partB = (double*)(base + a.lay.partB);
   w.partC = (double*)(base + a.lay.partC);
   w.partS = (double*)(base + a.lay.partS);
-  w.bar = (unsigned long long*)(base + a.lay.ctl);
-  w.slot = (int*)(base + a.lay.ctl + MF_CTL_SLOT_BYTES);
-  w.err = (int*)(base + a.lay.ctl + MF_CTL_ERR_BYTES);
+  char* ctl = a.team_ctl + (long)team * MF_CTL_BYTES;
+  w.bar = (unsigned long long*)ctl;
+  w.slot = (int*)(ctl + MF_CTL_SLOT_BYTES);
+  w.err = (int*)(ctl + MF_CTL_ERR_BYTES);
   return w;
 }
 
@@ -513,7 +517,8 @@ __device__ __forceinline__ int nE(long n) { return (int)((n + 1023) / 1024); }
 // ------------------------------------------------------------------------
 // Operator construction and set-up
 // ------------------------------------------------------------------------
-__device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+__device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds,
+                                        int team_size) {
   op.n = d.n;
   op.m = d.m;
   op.lda = d.n;
@@ -521,8 +526,18 @@ __device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstD
   op.b = a.b ? a.b + d.m_off : nullptr;
   op.D = w.D;
   op.Yv = w.Yv;
+  op.PT = w.PT;
   op.RB = a.tile_param > 0 ? (a.tile_param > DN_RBMAX ? DN_RBMAX : a.tile_param) : 8;
   op.lds = (double*)lds;
+  op.fused = (d.n <= DN_FUSED_MAXN) && ((d.n & 1) == 0) && a.lay.pt_chunks > 0;
+  // fused: chunks of whole row blocks, at most one per workgroup of the team
+  const long blocks = (d.m + DN_FB - 1) / DN_FB;
+  long nc = team_size < a.lay.pt_chunks ? team_size : a.lay.pt_chunks;
+  if (nc > blocks) nc = blocks;
+  if (nc < 1) nc = 1;
+  const long bpc = (blocks + nc - 1) / nc;
+  op.chunk_rows = (int)(bpc * DN_FB);
+  op.nchunk = (int)((d.m + op.chunk_rows - 1) / op.chunk_rows);
 }
 
 __device__ __forceinline__ int ilog2(long v) {
@@ -531,7 +546,8 @@ __device__ __forceinline__ int ilog2(long v) {
   return l;
 }
 
-__device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds) {
+__device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds,
+                                        int) {
   op.n = d.n;
   op.m = d.m;
   op.H = (int)(d.n >> 1);
@@ -556,6 +572,8 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.tw.lo = (const cplx*)lds + PD_TILE_CPLX;
   op.tw.hi = op.tw.lo + (1 << a.tw_lo_bits);
   op.tw.lo_bits = a.tw_lo_bits;
+  op.msk = (unsigned char*)(op.tw.hi + (1 << (a.tw_log2n_max + 2 - a.tw_lo_bits)));
+  op.cur_k1a = 0;
   op.tw.scale_shift = a.tw_log2n_max - op.logn;
   op.tile = (cplx*)lds;
   op.a0 = sqrt(1.0 / (double)d.n);
@@ -606,7 +624,7 @@ __device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, con
 
 // rho: Frobenius-closest scalar to A^T A (Section 5, before eq. (eq:ne2_P)).
 __device__ __forceinline__ double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
-  const int ni = op.nB();
+  const int ni = op.nF();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     const double s = op.frob_block(it);
     if (threadIdx.x == 0) w.partS[(long)it * MF_MAXK] = s;
@@ -774,7 +792,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
   const TeamWS w = make_ws(a, cx.t.id);
   const DevParams& prm = a.prm;
   OP op;
-  make_op(op, a, d, w, lds);
+  make_op(op, a, d, w, lds, cx.t.size);
   const long n = d.n;
   double2* Z = a.state ? (double2*)(a.state + 4 * d.n_off) : w.Zs;
   double2* S = a.state ? (double2*)(a.state + 4 * d.n_off + 2 * d.n) : w.Ss;
@@ -936,7 +954,7 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
   const TeamWS w = make_ws(a, cx.t.id);
   const DevParams& prm = a.prm;
   OP op;
-  make_op(op, a, d, w, lds);
+  make_op(op, a, d, w, lds, cx.t.size);
   const long n = d.n;
   const double2* Z = (const double2*)(a.state + 4 * d.n_off);
   const double2* S = (const double2*)(a.state + 4 * d.n_off + 2 * d.n);

@@ -69,6 +69,8 @@ struct mfipm_handle {
   double last_ms;
   int occ[2][2];             // [op][bwd] max resident workgroups per CU
   size_t scratch_lane[2][2];  // [op][bwd] private bytes per lane
+  // twiddle tables (device, owned by the handle), one per table resolution
+  cplx* tw[32];
 };
 
 // Upper bound on private (scratch) memory of one dispatch: all workgroups of a
@@ -99,8 +101,9 @@ inline int ilog2_host(long long v) {
 }
 inline bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
 
-// Team region layout for the largest instance of a call.
-TeamLayout team_layout(int op_kind, long long n, long long m) {
+// Team region layout for the largest instance of a call.  pt_chunks: chunk
+// capacity of the dense fused path's partial-product buffer.
+TeamLayout team_layout(int op_kind, long long n, long long m, int pt_chunks) {
   TeamLayout L{};
   size_t off = 0;
   auto take = [&](long& field, size_t bytes) {
@@ -119,9 +122,12 @@ TeamLayout team_layout(int op_kind, long long n, long long m) {
   if (op_kind == MFIPM_OP_DENSE) {
     take(L.D, (size_t)n * sizeof(double));
     take(L.Yv, (size_t)m * sizeof(double));
+    L.pt_chunks = n <= DN_FUSED_MAXN ? pt_chunks : 0;
+    take(L.PT, (size_t)L.pt_chunks * (size_t)n * sizeof(double));
     L.Y1 = L.Y2 = L.mask = L.bt = L.XS = 0;
   } else {
-    L.D = L.Yv = 0;
+    L.D = L.Yv = L.PT = 0;
+    L.pt_chunks = 0;
     take(L.Y1, (size_t)n * sizeof(double));  // n/2 complex
     take(L.Y2, (size_t)n * sizeof(double));
     take(L.mask, (size_t)n);
@@ -134,13 +140,14 @@ TeamLayout team_layout(int op_kind, long long n, long long m) {
   take(L.partB, pb);
   take(L.partC, pb);
   take(L.partS, pb);
-  take(L.ctl, MF_CTL_BYTES);
   L.stride = (long)off;
   return L;
 }
 
+// Workspace: [control: global words (256 B) + one block per team]
+//            [reports][descriptors + launch order][team regions]
 struct GlobalLayout {
-  size_t ctl, info, inst, order, tw_lo, tw_hi, teams, total;
+  size_t ctl, info, inst, order, teams, total;
   int lo_bits;
   long long hi_count;
 };
@@ -149,29 +156,32 @@ GlobalLayout global_layout(int op_kind, long long n_max, int batch, int teams, c
   GlobalLayout g{};
   size_t off = 0;
   g.ctl = off;
-  off += align_up(256);
+  off += align_up(256 + (size_t)teams * MF_CTL_BYTES);
   g.info = off;
   off += align_up((size_t)batch * sizeof(DevInfo));
   g.inst = off;
-  off += align_up((size_t)batch * sizeof(InstDesc));
-  g.order = off;
-  off += align_up((size_t)batch * sizeof(int));
+  g.order = off + (size_t)batch * sizeof(InstDesc);
+  off += align_up((size_t)batch * (sizeof(InstDesc) + sizeof(int)));
   g.lo_bits = 0;
   g.hi_count = 0;
-  g.tw_lo = g.tw_hi = off;
   if (op_kind == MFIPM_OP_PDCT) {
     const int lm = ilog2_host(n_max) + 2;  // table resolution 4 n_max
     g.lo_bits = (lm + 1) / 2;
     g.hi_count = 1LL << (lm - g.lo_bits);
-    g.tw_lo = off;
-    off += align_up(((size_t)1 << g.lo_bits) * sizeof(cplx));
-    g.tw_hi = off;
-    off += align_up((size_t)g.hi_count * sizeof(cplx));
   }
   g.teams = off;
   off += (size_t)teams * (size_t)tl.stride;
   g.total = off;
   return g;
+}
+
+// Chunk capacity of the dense fused path: one chunk per workgroup of a
+// single-instance team (up to the resident grid), at most 64 for batches.
+int pt_chunks_for(const mfipm_handle* h, int bwd, int batch, long long m_max) {
+  const long long blocks = (m_max + DN_FB - 1) / DN_FB;
+  const long long gmax = std::max(1, h->occ[MFIPM_OP_DENSE][bwd] * h->num_cu);
+  const long long cap = batch == 1 ? gmax : 64;
+  return (int)std::max(1LL, std::min(blocks, cap));
 }
 
 int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch) {
@@ -197,7 +207,8 @@ size_t dyn_lds(int op_kind, int lo_bits = -1, long long hi_count = 0) {
     lo_bits = (lm + 1) / 2;
     hi_count = 1LL << (lm - lo_bits);
   }
-  return (size_t)PD_TILE_CPLX * sizeof(cplx) + (((size_t)1 << lo_bits) + (size_t)hi_count) * sizeof(cplx);
+  return (size_t)PD_TILE_CPLX * sizeof(cplx) + (((size_t)1 << lo_bits) + (size_t)hi_count) * sizeof(cplx) +
+         PD_MASK_BYTES;
 }
 
 void fill_twiddles(std::vector<cplx>& lo, std::vector<cplx>& hi, int lm, int lo_bits) {
@@ -216,9 +227,33 @@ void fill_twiddles(std::vector<cplx>& lo, std::vector<cplx>& hi, int lm, int lo_
   }
 }
 
+// Device twiddle tables of resolution 2^lm (lo part then hi part), built on
+// the host once per resolution and kept by the handle.
+const cplx* twiddle_tables(mfipm_handle* h, int lm, int lo_bits) {
+  if (lm < 0 || lm >= 32) return nullptr;
+  if (h->tw[lm]) return h->tw[lm];
+  std::vector<cplx> lo, hi;
+  fill_twiddles(lo, hi, lm, lo_bits);
+  cplx* d = nullptr;
+  if (hipMalloc(&d, (lo.size() + hi.size()) * sizeof(cplx)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, lo.data(), lo.size() * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d + lo.size(), hi.data(), hi.size() * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  h->tw[lm] = d;
+  return d;
+}
+
 // Items of the widest pass of one instance (used to size a single team).
 long long widest_pass(int op_kind, long long n, long long m, int tile) {
   if (op_kind == MFIPM_OP_DENSE) {
+    if (n <= DN_FUSED_MAXN) {
+      // about 256 KiB of A per workgroup, at least 32 and at most one block each
+      const long long blocks = (m + DN_FB - 1) / DN_FB;
+      const long long want = std::max(32LL, (m * n * 8) >> 18);
+      return std::max(1LL, std::min(blocks, want));
+    }
     const int RB = tile > 0 ? std::min(tile, DN_RBMAX) : 8;
     return std::max((m + RB - 1) / RB, (n + DN_CB - 1) / DN_CB);
   }
@@ -306,13 +341,14 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   if (h->scratch_lane[P.op_kind][bwd] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
     return MFIPM_ERR_HIP;
 
-  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max);
+  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max));
   const GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
   if (ws_bytes < gl.total) return MFIPM_ERR_WORKSPACE_TOO_SMALL;
 
   char* base = (char*)ws;
-  // host-side tables
-  std::vector<InstDesc> inst(P.batch);
+  // host-side tables: descriptors followed by the launch order (one upload)
+  std::vector<char> desc((size_t)P.batch * (sizeof(InstDesc) + sizeof(int)));
+  InstDesc* inst = reinterpret_cast<InstDesc*>(desc.data());
   std::vector<int> order(P.batch);
   for (int i = 0; i < P.batch; ++i) {
     inst[i].n = P.n_off[i + 1] - P.n_off[i];
@@ -322,26 +358,23 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     inst[i].a_off = (P.op_kind == MFIPM_OP_DENSE && !P.shared_op) ? P.a_off[i] : 0;
     inst[i].tau = P.tau ? P.tau[i] : 0.0;
   }
-  std::iota(order.begin(), order.end(), 0);
+  for (int i = 0; i < P.batch; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
     const double cu = (double)inst[u].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[u].m : 1);
     const double cv = (double)inst[v].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[v].m : 1);
     return cu > cv;
   });
   hipStream_t s = h->stream;
-  HIP_TRY(hipMemcpyAsync(base + gl.inst, inst.data(), sizeof(InstDesc) * P.batch, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(base + gl.order, order.data(), sizeof(int) * P.batch, hipMemcpyHostToDevice, s));
-  std::vector<cplx> lo, hi;
-  int logn_max = ilog2_host(P.n_max);
+  std::memcpy(desc.data() + (size_t)P.batch * sizeof(InstDesc), order.data(), sizeof(int) * P.batch);
+  HIP_TRY(hipMemcpyAsync(base + gl.inst, desc.data(), desc.size(), hipMemcpyHostToDevice, s));
+  const int logn_max = ilog2_host(P.n_max);
+  const cplx* tw = nullptr;
   if (P.op_kind == MFIPM_OP_PDCT) {
-    fill_twiddles(lo, hi, logn_max + 2, gl.lo_bits);
-    HIP_TRY(hipMemcpyAsync(base + gl.tw_lo, lo.data(), lo.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + gl.tw_hi, hi.data(), hi.size() * sizeof(cplx), hipMemcpyHostToDevice, s));
+    tw = twiddle_tables(h, logn_max + 2, gl.lo_bits);
+    if (!tw) return MFIPM_ERR_HIP;
   }
-  // zero the control words: queue head, abort flag, team barriers
-  HIP_TRY(hipMemsetAsync(base + gl.ctl, 0, 256, s));
-  for (int t = 0; t < num_teams; ++t)
-    HIP_TRY(hipMemsetAsync(base + gl.teams + (size_t)t * tl.stride + tl.ctl, 0, MF_CTL_BYTES, s));
+  // zero the control words: queue head, abort flag, team barriers and slots
+  HIP_TRY(hipMemsetAsync(base + gl.ctl, 0, 256 + (size_t)num_teams * MF_CTL_BYTES, s));
 
   KArgs a{};
   a.inst = (const InstDesc*)(base + gl.inst);
@@ -361,9 +394,10 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   a.grad_tau = grad_tau;
   std::memcpy(&a.prm, &h->prm, sizeof(DevParams));
   a.team_base = base + gl.teams;
+  a.team_ctl = base + gl.ctl + 256;
   a.lay = tl;
-  a.tw_lo = (const cplx*)(base + gl.tw_lo);
-  a.tw_hi = (const cplx*)(base + gl.tw_hi);
+  a.tw_lo = tw;
+  a.tw_hi = tw ? tw + ((size_t)1 << gl.lo_bits) : nullptr;
   a.tw_lo_bits = gl.lo_bits;
   a.tw_log2n_max = logn_max;
   a.team_size = team_size;
@@ -479,6 +513,8 @@ int mfipm_destroy(mfipm_handle* h) {
   if (!h) return MFIPM_OK;
   (void)hipEventDestroy(h->ev0);
   (void)hipEventDestroy(h->ev1);
+  for (int i = 0; i < 32; ++i)
+    if (h->tw[i]) (void)hipFree(h->tw[i]);
   delete h;
   return MFIPM_OK;
 }
@@ -499,7 +535,7 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
   if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
   size_t best = 0;
   for (int bwd = 0; bwd < 2; ++bwd) {
-    const TeamLayout tl = team_layout(op_kind, max_n, max_m);
+    const TeamLayout tl = team_layout(op_kind, max_n, max_m, pt_chunks_for(h, bwd, batch, max_m));
     const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch), tl);
     best = std::max(best, gl.total);
   }

@@ -1,18 +1,28 @@
 // Dense operator: explicit row-major m x n matrix A (leading dimension lda).
-// The Newton-operator product K d = A^T (A d) and the residual
-// A^T (A x - b) are two streaming passes over A, split at a team barrier:
-//   pass A: d (from the functor, one value per index) -> D        (index tiles)
-//   pass B: y = A D (- b) -> Yv, partial sums of y^2, b.y        (row blocks)
-//   pass C: t = A^T Yv -> functor epilogue                        (column blocks)
-// Rows are read with all 256 lanes of a workgroup on consecutive columns;
-// columns are read by DN_RG row-groups x 64 lanes (512-byte row segments).
+//
+// Fused path (n <= DN_FUSED_MAXN): the Newton-operator product
+// t = A^T (A d) and the residual A^T (A x - b) read A once:
+//   pass A: d (from the functor) -> D                               (index tiles)
+//   pass B: each item is a contiguous chunk of rows.  The workgroup holds
+//           its columns of d in registers (thread t owns columns t + 512 j),
+//           streams the chunk in blocks of DN_FB rows, reduces y_r = A_r . d
+//           over the workgroup, and accumulates t_acc += A_blk^T y_blk in
+//           registers; one partial t per chunk is written at the end.
+//           Partial sums of y^2 (and b.y for the residual).
+//   pass C: t = sum over chunks of the partials (fixed order) -> functor
+//           epilogue                                                (index tiles)
+// Two-pass path (larger n): pass B = row-block GEMV y = A d -> Yv, pass C =
+// column-block GEMV^T t = A^T Yv with DN_RG row groups x 64 lanes.
 #pragma once
 #include "common.h"
 
-#define DN_TA 1024   // indices per pass-A item
-#define DN_CB 64     // columns per pass-C item
-#define DN_RBMAX 16  // max rows per pass-B item
-#define DN_RG (MF_THREADS / 64)  // row groups of pass C
+#define DN_TA 1024   // indices per pass-A / fused pass-C item
+#define DN_CB 64     // columns per two-pass pass-C item
+#define DN_RBMAX 16  // max rows per two-pass pass-B item
+#define DN_RG (MF_THREADS / 64)  // row groups of the two-pass pass C
+#define DN_CPT 16                // columns per thread held in registers (fused)
+#define DN_FUSED_MAXN (DN_CPT * MF_THREADS)
+#define DN_FB 2                  // rows per fused block
 
 enum { DB_HAPPLY = 0, DB_RESID = 1, DB_OUT = 2 };
 
@@ -24,12 +34,17 @@ struct OpDense {
   const double* __restrict__ b;
   double* D;
   double* Yv;
+  double* PT;  // fused: partial t, nchunk x n
   int RB;
-  double* lds;  // reduction scratch: >= MF_WAVES * DN_RBMAX + DN_RG * DN_CB doubles
+  int fused;
+  int nchunk;      // fused: chunks (pass-B items)
+  int chunk_rows;  // fused: rows per chunk (multiple of DN_FB)
+  double* lds;     // reduction scratch: >= MF_WAVES * DN_RBMAX + DN_RG * DN_CB doubles
 
   __device__ int nA() const { return (int)((n + DN_TA - 1) / DN_TA); }
-  __device__ int nB() const { return (int)((m + RB - 1) / RB); }
+  __device__ int nB() const { return fused ? nchunk : (int)((m + RB - 1) / RB); }
   __device__ int nC() const { return (int)((n + DN_CB - 1) / DN_CB); }
+  __device__ int nF() const { return (int)((m + 7) / 8); }
 
   template <class F>
   __device__ __forceinline__ void passA(int item, F& f) {
@@ -48,10 +63,128 @@ struct OpDense {
     }
   }
 
+  // ---- fused pass B over one chunk of rows ----
+  // Thread t owns the column pairs p = t + MF_THREADS k, k < CPT/2 (columns 2p, 2p+1,
+  // loaded as one 16-byte double2).  acc valid in thread 0: acc[0] += sum y^2,
+  // acc[1] += sum b*y (RESID).  Mode OUT writes y to `out` and skips the
+  // transposed product.
+  template <int CPT>
+  __device__ __forceinline__ void passB_fused(int item, int mode, double (&acc)[2], double* out) {
+    constexpr int KP = CPT / 2;
+    const long r_begin = (long)item * chunk_rows;
+    const long r_end = (r_begin + chunk_rows) < m ? (r_begin + chunk_rows) : m;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long npair = n >> 1;  // n is even on this path
+    double2 dv[KP], tacc[KP];
+    const double2* D2 = reinterpret_cast<const double2*>(D);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const long p = tid + (long)k * MF_THREADS;
+      dv[k] = p < npair ? D2[p] : make_double2(0.0, 0.0);
+      tacc[k] = make_double2(0.0, 0.0);
+    }
+    double* red = lds;  // [2 parities][MF_WAVES][DN_FB]
+    int parity = 0;
+    for (long r0 = r_begin; r0 < r_end; r0 += DN_FB) {
+      double2 a[DN_FB][KP];
+      double s[DN_FB];
+#pragma unroll
+      for (int r = 0; r < DN_FB; ++r) {
+        const bool rv = (r0 + r) < r_end;
+        const double2* row = reinterpret_cast<const double2*>(A + (r0 + r) * lda);
+        double sr = 0.0;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          const long p = tid + (long)k * MF_THREADS;
+          a[r][k] = (rv && p < npair) ? row[p] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < KP; ++k) sr += a[r][k].x * dv[k].x + a[r][k].y * dv[k].y;
+        s[r] = sr;
+      }
+#pragma unroll
+      for (int r = 0; r < DN_FB; ++r) {
+        const double v = wave_reduce(0, s[r]);
+        if (lane == 0) red[(parity * MF_WAVES + wave) * DN_FB + r] = v;
+      }
+      __syncthreads();
+      double y[DN_FB];
+#pragma unroll
+      for (int r = 0; r < DN_FB; ++r) {
+        double t = red[(parity * MF_WAVES) * DN_FB + r];
+        for (int w = 1; w < MF_WAVES; ++w) t += red[(parity * MF_WAVES + w) * DN_FB + r];
+        const bool rv = (r0 + r) < r_end;
+        if (rv && mode == DB_RESID) {
+          const double bb = b[r0 + r];
+          t -= bb;
+          if (tid == 0) acc[1] += bb * t;
+        }
+        if (!rv) t = 0.0;
+        if (tid == 0) acc[0] += t * t;
+        if (rv && mode == DB_OUT && tid == 0) out[r0 + r] = t;
+        y[r] = t;
+      }
+      parity ^= 1;  // the other half of `red` is written next; no second barrier
+      if (mode != DB_OUT) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          double2 t = tacc[k];
+#pragma unroll
+          for (int r = 0; r < DN_FB; ++r) {
+            t.x += a[r][k].x * y[r];
+            t.y += a[r][k].y * y[r];
+          }
+          tacc[k] = t;
+        }
+      }
+    }
+    if (mode != DB_OUT) {
+      double2* pt = reinterpret_cast<double2*>(PT + (long)item * n);
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const long p = tid + (long)k * MF_THREADS;
+        if (p < npair) pt[p] = tacc[k];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- fused pass C: t = sum of chunk partials -> functor ----
+  // Items of DN_CB columns; DN_RG groups of 64 lanes split the chunks
+  // (group g sums chunks g, g + DN_RG, ...), then lane-column sums of the
+  // groups in order feed the functor.
+  template <class F>
+  __device__ __forceinline__ void passC_fused(int item, F& f) {
+    const long c0 = (long)item * DN_CB;
+    const int col = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const long c = c0 + col;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < n) {
+      int ch = rg;
+      for (; ch + 3 * DN_RG < nchunk; ch += 4 * DN_RG) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a4[u] += PT[(long)(ch + DN_RG * u) * n + c];
+      }
+      for (; ch < nchunk; ch += DN_RG) a4[0] += PT[(long)ch * n + c];
+    }
+    double* red = lds + MF_WAVES * DN_RBMAX;
+    red[rg * 64 + col] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    __syncthreads();
+    if (rg == 0 && c < n) {
+      double t = red[col];
+      for (int g = 1; g < DN_RG; ++g) t += red[g * 64 + col];
+      typename F::In in;
+      f.load(c, in);
+      f.scatter(c, t, in);
+    }
+    __syncthreads();
+  }
+
+  // ---- two-pass path ----
   // y_r = A[r,:] . D for the rows of the block; mode RESID subtracts b,
   // mode OUT writes y to `out` instead of Yv.  acc[0] += sum y^2,
   // acc[1] += sum b*y (RESID).  Results valid in thread 0.
-  __device__ __forceinline__ void passB(int item, int mode, double (&acc)[2], double* out) {
+  __device__ __forceinline__ void passB_rows(int item, int mode, double (&acc)[2], double* out) {
     const long r0 = (long)item * RB;
     const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
     double s[DN_RBMAX];
@@ -90,7 +223,7 @@ struct OpDense {
   }
 
   template <class F>
-  __device__ __forceinline__ void passC(int item, F& f) {
+  __device__ __forceinline__ void passC_cols(int item, F& f) {
     const long c0 = (long)item * DN_CB;
     const int col = threadIdx.x & 63, rg = threadIdx.x >> 6;
     const long c = c0 + col;
@@ -116,10 +249,24 @@ struct OpDense {
     __syncthreads();
   }
 
-  // sum of squares of the rows of a block (setup: ||A||_F^2), thread 0
+  __device__ __forceinline__ void passB(int item, int mode, double (&acc)[2], double* out) {
+    if (fused) {
+      if (n <= (DN_CPT / 2) * MF_THREADS) passB_fused<DN_CPT / 2>(item, mode, acc, out);
+      else passB_fused<DN_CPT>(item, mode, acc, out);
+    } else {
+      passB_rows(item, mode, acc, out);
+    }
+  }
+  template <class F>
+  __device__ __forceinline__ void passC(int item, F& f) {
+    if (fused) passC_fused(item, f);
+    else passC_cols(item, f);
+  }
+
+  // sum of squares of 8 rows (set-up: ||A||_F^2), returned in thread 0
   __device__ __forceinline__ double frob_block(int item) {
-    const long r0 = (long)item * RB;
-    const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
+    const long r0 = (long)item * 8;
+    const int nr = (int)((m - r0) < 8 ? (m - r0) : 8);
     double s = 0.0;
     for (int r = 0; r < nr; ++r)
       for (long c = threadIdx.x; c < n; c += MF_THREADS) {

@@ -27,6 +27,10 @@
 
 #define PD_TILE_CPLX 4096  // LDS tile: 4096 complex doubles = 64 KiB
 #define PD_EPT (PD_TILE_CPLX / MF_THREADS)  // tile elements per thread
+#ifndef PD_U
+#define PD_U 2  // gather/scatter units in flight per thread
+#endif
+#define PD_MASK_BYTES 8192  // LDS staging of one pass-B item's mask (4 N2 <= 8192)
 
 // ------------------------------- radix kernels --------------------------------
 template <int R>
@@ -130,13 +134,17 @@ __device__ __forceinline__ void stockham_pass(cplx* buf, int L, int Ls, int coun
 
 // Unnormalised DFT (sign -1) or inverse DFT (sign +1) of `count` sequences of
 // length L = 2^log2L (count * L <= 4096).  Caller synchronises before.
+// Radix 8 while at least three factors of two remain, then 4 or 2: the
+// fewest passes (each pass costs two workgroup barriers and an LDS round trip,
+// which outweighs idle lanes on small tiles).
 __device__ __forceinline__ void lds_fft(cplx* buf, int log2L, int count, int istride, int sstride, int sign,
                                const Twiddle& tw, int log2M) {
   const int L = 1 << log2L;
   int Ls = 1, lg = 0;
   while (Ls < L) {
-    const int rem = log2L - lg;
-    if (rem >= 3) {
+    int rem = log2L - lg;
+    if (rem > 3) rem = 3;
+    if (rem == 3) {
       stockham_pass<8>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 3);
       Ls <<= 3;
       lg += 3;
@@ -167,8 +175,16 @@ struct OpPdct {
   double* bt;           // spectral layout, n doubles
   double* XS;           // spectral layout, n doubles (forward output)
   Twiddle tw;
-  cplx* tile;  // LDS
+  cplx* tile;          // LDS
+  unsigned char* msk;  // LDS: mask of the current pass-B item, rows (k1a, k1b)
+  int cur_k1a;
   double a0, a1;
+
+  // mask value of coefficient owner (k, e), from the LDS copy of the item
+  __device__ __forceinline__ double mval(long k, int e) const {
+    const int k1 = (int)(k & (N1 - 1));
+    return (double)msk[(k1 == cur_k1a ? 0 : 2 * N2) + (int)((k >> l1) << 1) + e];
+  }
 
   __device__ int nA() const { return N2 >> 3; }
   __device__ int nB() const { return N1 >> 1; }
@@ -207,7 +223,7 @@ struct OpPdct {
   __device__ __forceinline__ void passA(int q, F& f) {
     double* td = reinterpret_cast<double*>(tile);
     const int units = 16 * N1;
-    constexpr int U = 2;
+    constexpr int U = PD_U;
     for (int base = 0; base < units; base += MF_THREADS * U) {
       typename F::In in[U];
       long idx[U];
@@ -246,7 +262,7 @@ struct OpPdct {
     lds_fft(tile, l1, 8, 8, 1, +1, tw, log2M());
     const double* td = reinterpret_cast<const double*>(tile);
     const int units = 16 * N1;
-    constexpr int U = 2;
+    constexpr int U = PD_U;
     for (int base = 0; base < units; base += MF_THREADS * U) {
       typename F::In in[U];
       long idx[U];
@@ -283,7 +299,7 @@ struct OpPdct {
         XS[p1] = XH;
         return;
       }
-      const double m0 = mask[p0], m1 = mask[p1];
+      const double m0 = mval(0, 0), m1 = mval(0, 1);
       double Y0 = m0 * X0, YH = m1 * XH;
       if (mode == PB_RESID) {
         const double b0 = bt[p0], b1 = bt[p1];
@@ -319,11 +335,11 @@ struct OpPdct {
       }
       return;
     }
-    double ya0 = mask[qa0] * xa0, ya1 = mask[qa1] * xa1;
+    double ya0 = mval(kA, 0) * xa0, ya1 = mval(kA, 1) * xa1;
     double yb0 = 0, yb1 = 0;
     if (!self) {
-      yb0 = mask[qb0] * xb0;
-      yb1 = mask[qb1] * xb1;
+      yb0 = mval(kB, 0) * xb0;
+      yb1 = mval(kB, 1) * xb1;
     }
     if (mode == PB_RESID) {
       const double ba0 = bt[qa0], ba1 = bt[qa1];
@@ -360,6 +376,15 @@ struct OpPdct {
   __device__ __forceinline__ void passB(int r, int mode, double (&acc)[2]) {
     const int k1a = r == 0 ? 0 : r;
     const int k1b = r == 0 ? (N1 >> 1) : N1 - r;
+    cur_k1a = k1a;
+    if (mode != PB_FWDOUT) {
+      // the item's mask bytes (two rows of 2 N2) to LDS, as 32-bit words
+      const unsigned* ga = reinterpret_cast<const unsigned*>(mask + (long)k1a * 2 * N2);
+      const unsigned* gb = reinterpret_cast<const unsigned*>(mask + (long)k1b * 2 * N2);
+      unsigned* ml = reinterpret_cast<unsigned*>(msk);
+      const int wpr = N2 >> 1;  // 32-bit words per row
+      for (int i = threadIdx.x; i < 2 * wpr; i += MF_THREADS) ml[i] = i < wpr ? ga[i] : gb[i - wpr];
+    }
     for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
       const int s = u2 >= N2;
       const int u = u2 - s * N2;
