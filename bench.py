@@ -45,6 +45,32 @@ def alg_bytes(kind: str, n: int, m: int, info: dict) -> float:
     return pcg + ipm
 
 
+def kernel_src_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1208_5435_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("src_hash") != kernel_src_hash():
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "pdct":
@@ -303,7 +329,7 @@ def main():
                    "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
                    "kernel_ms_min": round(float(np.min(kms)), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl),
                      "kernel": "k_mfipm<OpPdct,0>" if kind == "pdct" else "k_mfipm<OpDense,0>",
                      "alg_bytes_per_launch": ab},
     }
