@@ -116,8 +116,7 @@ def _pool_map(fn, items, workers=16):
         return list(ex.map(fn, items))
 
 
-def bench_batched_dense(args, torch, Solver):
-    """256 uneven dense instances in one launch vs one launch per instance."""
+def batched_dense_inputs(args, torch):
     import workloads as W
     sizes = W.batched_dense_sizes(batch=args.batch)
     t0 = time.perf_counter()
@@ -132,6 +131,12 @@ def bench_batched_dense(args, torch, Solver):
         A[a_off[j]:a_off[j + 1]].copy_(torch.from_numpy(i.A.reshape(-1)))
     b = torch.from_numpy(np.concatenate([i.b for i in insts])).to(dev)
     taus = np.array([i.tau for i in insts])
+    return insts, gen_s, dev, n_off, m_off, a_off, A, b, taus
+
+
+def bench_batched_dense(args, torch, Solver):
+    """256 uneven dense instances in one launch vs one launch per instance."""
+    insts, gen_s, dev, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
     solver = Solver(device=dev)
     solver.set_launch(args.workgroups, args.team, args.tile)
     run = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
@@ -241,6 +246,57 @@ def bench_grad(args, torch, Solver):
     }
 
 
+def tune_workload(args, torch, Solver):
+    """Autotunes the launch shape of one workload (forward, and backward for
+    the gradient batch) and writes it to the package's shipped table."""
+    from paper_1208_5435_amd import autotune
+    dev = torch.device("cuda", 0)
+    solver = Solver(device=dev)
+    out = args.tune_out or autotune.SHIPPED
+    jobs = []
+    if args.workload in ("pdct", "pdct_hdr", "dense"):
+        kind, inst, _ = make_workload(args.workload)
+        b = torch.from_numpy(inst.b).to(dev)
+        if kind == "dense":
+            A = torch.from_numpy(inst.A).to(dev)
+            call = lambda: solver.solve(b, inst.tau, A=A)  # noqa: E731
+            op = 0
+        else:
+            rows = torch.from_numpy(inst.rows).to(dev)
+            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n)  # noqa: E731
+            op = 1
+        jobs.append((solver.tune_key(op, inst.n, inst.m, 1, True), call,
+                     autotune.candidates(op, inst.n, inst.m, 1, solver.num_cu)))
+    elif args.workload == "grad":
+        import workloads as W
+        inst = W.config_dct_batch(n=args.grad_n, batch=32)
+        B, m = inst.b.shape
+        n_off = np.arange(B + 1, dtype=np.int64) * inst.n
+        m_off = np.arange(B + 1, dtype=np.int64) * m
+        rows = torch.from_numpy(inst.rows).to(dev)
+        b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
+        xt = torch.from_numpy(inst.x_true.reshape(-1)).to(dev)
+        res = solver.solve_batched(b, inst.tau, n_off, m_off, rows=rows, shared_op=True)
+        fwd = lambda: solver.solve_batched(b, inst.tau, n_off, m_off, rows=rows, shared_op=True)  # noqa: E731
+        bwd = lambda: solver.backward(res.state, res.x - xt, n_off, m_off, rows=rows, shared_op=True)  # noqa
+        cands = autotune.candidates(1, inst.n, m, B, solver.num_cu)
+        jobs.append((solver.tune_key(1, inst.n, m, B, True), fwd, cands))
+        jobs.append((solver.tune_key(1, inst.n, m, B, True, backward=True), bwd, cands))
+    elif args.workload == "batched_dense":
+        insts, _, _, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
+        call = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
+        nmax = int(np.diff(n_off).max())
+        mmax = int(np.diff(m_off).max())
+        jobs.append((solver.tune_key(0, nmax, mmax, len(insts), False), call,
+                     autotune.candidates(0, nmax, mmax, len(insts), solver.num_cu)))
+    else:
+        raise SystemExit("--tune supports pdct, pdct_hdr, dense, batched_dense, grad")
+    for key, call, cands in jobs:
+        best, ms, table = autotune.tune(solver, call, key, cands, reps=3, path=out, verbose=True)
+        print(json.dumps({"key": key, "best": best, "kernel_ms": ms,
+                          "table": [[list(s), round(t, 4)] for s, t in table]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,6 +311,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch shape of this workload and record it in the shipped table")
+    ap.add_argument("--tune-out", default=None, help="tuning table to write (default: the shipped one)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -267,6 +326,9 @@ def main():
     import torch
     from paper_1208_5435_amd import Solver
 
+    if args.tune:
+        tune_workload(args, torch, Solver)
+        return
     if args.workload in ("batched_dense", "grad"):
         fn = bench_batched_dense if args.workload == "batched_dense" else bench_grad
         print(json.dumps(fn(args, torch, Solver)), flush=True)

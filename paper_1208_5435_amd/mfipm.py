@@ -153,6 +153,9 @@ class Solver:
                                                          ctypes.c_void_p(self.stream.cuda_stream)))
         self.h = h
         self._ws = None
+        self._explicit = None  # launch shape fixed by the caller
+        self.arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        self.num_cu = torch.cuda.get_device_properties(self.device).multi_processor_count
 
     def close(self):
         if getattr(self, "h", None):
@@ -171,7 +174,24 @@ class Solver:
         _check("mfipm_set_params", self.lib.mfipm_set_params(self.h, ctypes.byref(self.params)))
 
     def set_launch(self, workgroups=0, team_size=0, tile=0):
-        _check("mfipm_set_launch", self.lib.mfipm_set_launch(self.h, workgroups, team_size, tile))
+        """Fixes the launch shape for later calls; (0, 0, 0) returns to the
+        tuned table (or the library's own choice when nothing is tuned)."""
+        shape = (int(workgroups), int(team_size), int(tile))
+        self._explicit = None if shape == (0, 0, 0) else shape
+        _check("mfipm_set_launch", self.lib.mfipm_set_launch(self.h, *shape))
+
+    def tune_key(self, op_kind, n_max, m_max, batch, shared, backward=False):
+        from . import autotune
+        return autotune.make_key(self.arch, op_kind, n_max, m_max, batch, shared, backward)
+
+    def _apply_shape(self, op_kind, n_max, m_max, batch, shared, backward=False):
+        from . import autotune
+        shape = self._explicit
+        if shape is None:
+            shape = autotune.lookup(self.tune_key(op_kind, n_max, m_max, batch, shared, backward)) \
+                or (0, 0, 0)
+        _check("mfipm_set_launch", self.lib.mfipm_set_launch(self.h, *shape))
+        return shape
 
     def last_kernel_ms(self) -> float:
         return float(self.lib.mfipm_last_kernel_ms(self.h))
@@ -204,6 +224,7 @@ class Solver:
             raise ValueError("b has the wrong length")
         x = torch.empty(int(op.n), dtype=torch.float64, device=self.device)
         state = torch.empty(4 * int(op.n), dtype=torch.float64, device=self.device) if want_state else None
+        self._apply_shape(kind, int(op.n), m, 1, True)
         ws, nb = self.workspace(kind, int(op.n), m, 1)
         info = Info()
         rc = self.lib.mfipm_solve(self.h, ctypes.byref(op), _ptr(b), float(tau), _ptr(x), _ptr(state),
@@ -232,6 +253,7 @@ class Solver:
         state = torch.empty(4 * N, dtype=torch.float64, device=self.device) if want_state else None
         ns = np.diff(n_off)
         ms = np.diff(m_off)
+        self._apply_shape(kind, int(ns.max()), int(ms.max()), batch, shared_op)
         ws, nb = self.workspace(kind, int(ns.max()), int(ms.max()), batch)
         infos = (Info * batch)()
         rc = self.lib.mfipm_solve_batched(
@@ -261,6 +283,7 @@ class Solver:
         grad_tau = torch.empty(batch, dtype=torch.float64, device=self.device)
         ns = np.diff(n_off)
         ms = np.diff(m_off)
+        self._apply_shape(kind, int(ns.max()), int(ms.max()), batch, shared_op, backward=True)
         ws, nb = self.workspace(kind, int(ns.max()), int(ms.max()), batch)
         infos = (Info * batch)()
         rc = self.lib.mfipm_backward(

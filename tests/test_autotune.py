@@ -1,0 +1,67 @@
+"""Autotuner host logic (CPU) and launch-shape invariance (GPU)."""
+import numpy as np
+import pytest
+
+from paper_1208_5435_amd import autotune
+
+
+def test_candidates_valid():
+    for n in (64, 1024, 1 << 16, 1 << 20):
+        c = autotune.candidates(1, n, n // 4, 1)
+        assert c
+        lh = int(np.log2(n)) - 1
+        for wg, ts, tile in c:
+            assert ts == 0 and wg >= 0
+            assert 1 <= tile <= 9 and 3 <= lh - tile <= 11
+    c = autotune.candidates(0, 8192, 2048, 256)
+    assert all(wg == 0 and ts >= 1 for wg, ts, _ in c)
+
+
+def test_store_and_lookup(tmp_path, monkeypatch):
+    path = str(tmp_path / "cache.json")
+    monkeypatch.setenv("MFIPM_TUNE_CACHE", path)
+    key = autotune.make_key("gfx950", 1, 4096, 1024, 1, True)
+    assert autotune.make_key("gfx950", 1, 4096, 1024, 1, True, backward=True) != key
+    autotune.store(key, (64, 0, 5), 1.25)
+    assert autotune.lookup(key) == (64, 0, 5)
+    assert autotune.lookup(key + "x") is None
+
+
+def test_shipped_table_well_formed():
+    import json
+    import os
+    if not os.path.exists(autotune.SHIPPED):
+        pytest.skip("no shipped table")
+    d = json.load(open(autotune.SHIPPED))
+    for k, v in d.items():
+        assert k.startswith("gfx") and len(v["shape"]) == 3 and v["kernel_ms"] > 0
+
+
+@pytest.mark.gpu
+def test_workgroup_count_does_not_change_result(gpu_lib):
+    """Partial DCT: items are reduced in a fixed order, so the number of
+    workgroups of the team changes no bit of the answer.  Dense: the fused
+    operator splits rows into one chunk per workgroup, so the summation order
+    (and the last bits) follow the workgroup count; the answers agree to the
+    parity bar."""
+    import workloads as W
+    from paper_1208_5435_amd import Solver
+    s = Solver()
+    inst = W.dct_instance(1 << 14, 1 << 12, 160, seed=77)
+    xs = []
+    for wg in (8, 32, 128):
+        s.set_launch(wg, 0, 0)
+        r = s.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n)
+        xs.append(r.x.cpu().numpy())
+    s.set_launch(0, 0, 0)
+    d = W.dense_instance(200, 1000, 10, seed=78)
+    xd = []
+    for wg in (4, 16, 50):
+        s.set_launch(wg, 0, 0)
+        r = s.solve(d.b, d.tau, A=d.A)
+        xd.append(r.x.cpu().numpy())
+    s.set_launch(0, 0, 0)
+    s.close()
+    assert all(np.array_equal(xs[0], x) for x in xs[1:])
+    for x in xd[1:]:
+        assert np.linalg.norm(x - xd[0]) <= 1e-6 * np.linalg.norm(xd[0])
