@@ -7,7 +7,7 @@
 
 #define MF_THREADS 512
 #define MF_WAVES (MF_THREADS / 64)
-#define MF_MAXK 4  // partial-sum slots per pass
+#define MF_MAXK 6  // partial-sum slots per pass
 #define MF_RED_DOUBLES (MF_WAVES * MF_MAXK + MF_MAXK)
 
 // Status / flag values shared with the host driver.

@@ -45,8 +45,8 @@ struct InstDesc {
 // per-team workspace (device pointers)
 struct TeamWS {
   double2 *X, *R, *P, *TI, *DZ, *DS, *Zs, *Ss;
-  double *D, *Yv, *PT;
-  cplx *Y1, *Y2;
+  double *D, *Yv, *PT, *Dp0, *Dp1;
+  cplx *Y1, *Y1p, *Y2;
   unsigned char* mask;
   double *bt, *XS;
   double *partA, *partB, *partC, *partS;
@@ -56,7 +56,7 @@ struct TeamWS {
 };
 
 struct TeamLayout {  // byte offsets inside one team region
-  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Y1, Y2, mask, bt, XS, partA, partB, partC, partS;
+  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Dp0, Dp1, Y1, Y1p, Y2, mask, bt, XS, partA, partB, partC, partS;
   int pt_chunks;  // dense fused path: capacity of PT in chunks
   long stride;
 };
@@ -104,6 +104,9 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   w.D = (double*)(base + a.lay.D);
   w.Yv = (double*)(base + a.lay.Yv);
   w.PT = (double*)(base + a.lay.PT);
+  w.Dp0 = (double*)(base + a.lay.Dp0);
+  w.Dp1 = (double*)(base + a.lay.Dp1);
+  w.Y1p = (cplx*)(base + a.lay.Y1p);
   w.Y1 = (cplx*)(base + a.lay.Y1);
   w.Y2 = (cplx*)(base + a.lay.Y2);
   w.mask = (unsigned char*)(base + a.lay.mask);
@@ -125,40 +128,18 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
 // registers; gather()/scatter()/elem() compute, store, accumulate partials.
 // ------------------------------------------------------------------------
 
-// PCG pass A: y = P^{-1} r, p = y + beta p, d = p_u - p_v; acc0 += p^T Theta^{-1} p
-struct FPcgA {
-  static constexpr int K = 1;
-  struct In {
-    double2 r, ti, p;
-  };
-  double2* R;
-  double2* TI;
-  double2* P;
-  double beta, rho;
-  int first;
-  double acc[K];
-  __device__ void reset() { acc[0] = 0.0; }
-  __device__ void load(long i, In& in) const {
-    in.r = R[i];
-    in.ti = TI[i];
-    if (!first) in.p = P[i];
-  }
-  __device__ double gather(long i, const In& in) {
-    double yu, yv;
-    precond_apply(in.ti.x, in.ti.y, rho, in.r.x, in.r.y, yu, yv);
-    double2 p;
-    if (first) p = make_double2(yu, yv);
-    else p = make_double2(yu + beta * in.p.x, yv + beta * in.p.y);
-    P[i] = p;
-    acc[0] += in.ti.x * p.x * p.x + in.ti.y * p.y * p.y;
-    return p.x - p.y;
-  }
-};
-
-// PCG pass C: q = Theta^{-1} p + [t; -t]; x += alpha p; r -= alpha q;
-// acc0 += r^T P^{-1} r, acc1 += r^T r (new r)
-struct FPcgC {
-  static constexpr int K = 2;
+// PCG pass C (two passes per PCG iteration).  With t = (A^T A d)_i of the
+// current direction:
+//   y = P^{-1} r (r before the update), p = y + beta p_prev (p = y at the
+//   first iteration), q = Theta^{-1} p + [t; -t], x += alpha p, r -= alpha q,
+//   store x, r, p; then y' = P^{-1} r (new r) and return d' = y'_u - y'_v,
+//   whose column transform the operator prepares for the next iteration.
+// Partials: 0 r'^T y', 1 r'^T r', 2 y'^T Theta^{-1} y', 3 y'^T Theta^{-1} p,
+// 4 p^T Theta^{-1} p -- the next p^T Theta^{-1} p is
+// [2] + 2 beta' [3] + beta'^2 [4] once beta' is known.
+struct FPcgC2 {
+  static constexpr int K = 5;
+  static constexpr bool CHAIN = true;
   struct In {
     double2 p, ti, x, r;
   };
@@ -166,25 +147,39 @@ struct FPcgC {
   double2* TI;
   double2* X;
   double2* R;
-  double alpha, rho;
+  double alpha, beta, rho;
+  int first;
   double acc[K];
-  __device__ void reset() { acc[0] = acc[1] = 0.0; }
+  __device__ void reset() {
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = 0.0;
+  }
   __device__ void load(long i, In& in) const {
-    in.p = P[i];
+    if (!first) in.p = P[i];
     in.ti = TI[i];
     in.x = X[i];
     in.r = R[i];
   }
-  __device__ void scatter(long i, double t, const In& in) {
-    const double qu = in.ti.x * in.p.x + t, qv = in.ti.y * in.p.y - t;
-    const double2 x = make_double2(in.x.x + alpha * in.p.x, in.x.y + alpha * in.p.y);
+  __device__ double scatter(long i, double t, const In& in) {
+    double yu, yv;
+    precond_apply(in.ti.x, in.ti.y, rho, in.r.x, in.r.y, yu, yv);
+    double2 p;
+    if (first) p = make_double2(yu, yv);
+    else p = make_double2(yu + beta * in.p.x, yv + beta * in.p.y);
+    const double qu = in.ti.x * p.x + t, qv = in.ti.y * p.y - t;
+    const double2 x = make_double2(in.x.x + alpha * p.x, in.x.y + alpha * p.y);
     const double2 r = make_double2(in.r.x - alpha * qu, in.r.y - alpha * qv);
     X[i] = x;
     R[i] = r;
-    double yu, yv;
-    precond_apply(in.ti.x, in.ti.y, rho, r.x, r.y, yu, yv);
-    acc[0] += r.x * yu + r.y * yv;
+    P[i] = p;
+    double zu, zv;
+    precond_apply(in.ti.x, in.ti.y, rho, r.x, r.y, zu, zv);
+    acc[0] += r.x * zu + r.y * zv;
     acc[1] += r.x * r.x + r.y * r.y;
+    acc[2] += in.ti.x * zu * zu + in.ti.y * zv * zv;
+    acc[3] += in.ti.x * zu * p.x + in.ti.y * zv * p.y;
+    acc[4] += in.ti.x * p.x * p.x + in.ti.y * p.y * p.y;
+    return zu - zv;
   }
 };
 
@@ -241,9 +236,11 @@ struct FResA {
 // rhs = f_z + Z^{-1} f_s, f_z = s - [tau + g; tau - g], f_s = sigma mu - z s
 // (eqs. (fzfs), (redNewtonA)); store Theta^{-1} = s / z (not at the trial
 // point), r = rhs, x = 0.  acc0 = max |g|, acc1 += rhs^T rhs,
-// acc2 += rhs^T P^{-1} rhs.
+// acc2 += rhs^T P^{-1} rhs, acc3 += y^T Theta^{-1} y with y = P^{-1} rhs;
+// returns y_u - y_v, the first PCG direction's gather.
 struct FResC {
-  static constexpr int K = 3;
+  static constexpr int K = 4;
+  static constexpr bool CHAIN = true;
   struct In {
     double2 z, s, dz, ds, ti;
   };
@@ -259,7 +256,7 @@ struct FResC {
   double acc[K];
   __device__ void reset() {
     acc[0] = -__builtin_inf();
-    acc[1] = acc[2] = 0.0;
+    acc[1] = acc[2] = acc[3] = 0.0;
   }
   __device__ void load(long i, In& in) const {
     in.z = Z[i];
@@ -270,7 +267,7 @@ struct FResC {
       in.ti = TI[i];
     }
   }
-  __device__ void scatter(long i, double g, const In& in) {
+  __device__ double scatter(long i, double g, const In& in) {
     double2 zt = in.z, st = in.s, ti;
     if (trial) {
       zt = make_double2(in.z.x + aP * in.dz.x, in.z.y + aP * in.dz.y);
@@ -290,6 +287,8 @@ struct FResC {
     double yu, yv;
     precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
     acc[2] += ru * yu + rv * yv;
+    acc[3] += ti.x * yu * yu + ti.y * yv * yv;
+    return yu - yv;  // first gather of the PCG that follows
   }
 };
 
@@ -360,10 +359,12 @@ struct FOut {
   __device__ void elem(long i, const In& in) { x[i] = in.z.x - in.z.y; }
 };
 
-// Adjoint set-up: Theta^{-1} = s / z at the given state, r = rhs = [g; -g],
-// x = 0.  acc0 += rhs^T rhs, acc1 += rhs^T P^{-1} rhs.
+// Adjoint set-up (a pass-A functor): Theta^{-1} = s / z at the given state,
+// r = rhs = [g; -g], x = 0, and the first PCG gather d = y_u - y_v with
+// y = P^{-1} rhs.  acc0 += rhs^T P^{-1} rhs, acc1 += rhs^T rhs,
+// acc2 += y^T Theta^{-1} y.
 struct FBwdInit {
-  static constexpr int K = 2;
+  static constexpr int K = 3;
   struct In {
     double2 z, s;
     double g;
@@ -376,13 +377,13 @@ struct FBwdInit {
   double2* X;
   double rho;
   double acc[K];
-  __device__ void reset() { acc[0] = acc[1] = 0.0; }
+  __device__ void reset() { acc[0] = acc[1] = acc[2] = 0.0; }
   __device__ void load(long i, In& in) const {
     in.z = Z[i];
     in.s = S[i];
     in.g = gx[i];
   }
-  __device__ void elem(long i, const In& in) {
+  __device__ double gather(long i, const In& in) {
     const double2 ti = make_double2(in.s.x / in.z.x, in.s.y / in.z.y);
     TI[i] = ti;
     const double ru = in.g, rv = -in.g;
@@ -390,8 +391,10 @@ struct FBwdInit {
     X[i] = make_double2(0.0, 0.0);
     double yu, yv;
     precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
-    acc[0] += ru * ru + rv * rv;
-    acc[1] += ru * yu + rv * yv;
+    acc[0] += ru * yu + rv * yv;
+    acc[1] += ru * ru + rv * rv;
+    acc[2] += ti.x * yu * yu + ti.y * yv * yv;
+    return yu - yv;
   }
 };
 
@@ -458,16 +461,19 @@ __device__ __forceinline__ void run_C(Ctx& cx, OP& op, F& f, const int (&kinds)[
   }
 }
 
-// pass B: two sums (y^2, b.y)
+// pass B: two sums (y^2, b.y).  HAPPLY mode combines the direction first
+// (beta, first; see the operators).
 template <class OP>
-__device__ __forceinline__ void run_B(Ctx& cx, OP& op, int mode, double* part, double* out);
+__device__ __forceinline__ void run_B(Ctx& cx, OP& op, int mode, double* part, double* out, double beta = 0.0,
+                                      int first = 1);
 
 template <>
-__device__ __forceinline__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, double* out) {
+__device__ __forceinline__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, double* part, double* out,
+                                               double beta, int first) {
   const int ni = op.nB();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     double acc[2] = {0.0, 0.0};
-    op.passB(it, mode, acc, out);
+    op.passB(it, mode, acc, out, beta, first);
     if (threadIdx.x == 0) {
       part[(long)it * MF_MAXK + 0] = acc[0];
       part[(long)it * MF_MAXK + 1] = acc[1];
@@ -476,12 +482,13 @@ __device__ __forceinline__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, d
 }
 
 template <>
-__device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*) {
+__device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*, double beta,
+                                              int first) {
   const int ni = op.nB();
   const int kinds[2] = {0, 0};
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
     double acc[2] = {0.0, 0.0};
-    op.passB(it, mode, acc);
+    op.passB(it, mode, acc, beta, first);
     wg_reduce<2>(kinds, acc, cx.red);
     if (threadIdx.x == 0) {
       part[(long)it * MF_MAXK + 0] = acc[0];
@@ -489,6 +496,13 @@ __device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, dou
     }
   }
 }
+
+// the search-direction buffers of iteration `it` (dense: alternating d of p)
+__device__ __forceinline__ void op_direction(OpDense& op, const TeamWS& w, int it) {
+  op.Dp_prev = (it & 1) ? w.Dp0 : w.Dp1;
+  op.Dp_cur = (it & 1) ? w.Dp1 : w.Dp0;
+}
+__device__ __forceinline__ void op_direction(OpPdct&, const TeamWS&, int) {}
 
 // elementwise pass over [0, n), items of 1024 indices
 template <class F>
@@ -527,6 +541,8 @@ __device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstD
   op.D = w.D;
   op.Yv = w.Yv;
   op.PT = w.PT;
+  op.Dp_prev = w.Dp1;
+  op.Dp_cur = w.Dp0;
   op.RB = a.tile_param > 0 ? (a.tile_param > DN_RBMAX ? DN_RBMAX : a.tile_param) : 8;
   op.lds = (double*)lds;
   op.fused = (d.n <= DN_FUSED_MAXN) && ((d.n & 1) == 0) && a.lay.pt_chunks > 0;
@@ -565,6 +581,7 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.rows = a.rows + (a.shared_op ? 0 : d.m_off);
   op.b = a.b ? a.b + d.m_off : nullptr;
   op.Y1 = w.Y1;
+  op.Y1p = w.Y1p;
   op.Y2 = w.Y2;
   op.mask = w.mask;
   op.bt = w.bt;
@@ -641,16 +658,23 @@ __device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& a
 }
 
 // ------------------------------------------------------------------------
-// PCG on (Theta^{-1} + F F^T) x = rhs with the block preconditioner.
-// On entry R = rhs, X = 0, TI set; rhs2 = rhs^T rhs, rty = rhs^T P^{-1} rhs.
+// PCG on (Theta^{-1} + F F^T) x = rhs with the block preconditioner
+// (Section 5), two team barriers per iteration.  On entry R = rhs, X = 0,
+// TI set, and the operator holds the first gather d(y0) (y0 = P^{-1} rhs)
+// from the pass that built rhs; rhs2 = ||rhs||^2, gamma = rhs^T y0,
+// yty = y0^T Theta^{-1} y0.  Per iteration:
+//   pass B: combine the direction's transform (y + beta p), operator middle
+//           stage, partial ||A d||^2 (so p^T H p = p^T Theta^{-1} p + ||A d||^2)
+//   pass C: operator last stage, q, x and r updates, next y and its gather,
+//           partial dot products for beta and p^T Theta^{-1} p.
 // Returns a status (0 = ok); *iters = operator applies.
 // ------------------------------------------------------------------------
 template <class OP>
-__device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit, double rhs2,
-                       double rty, int* iters) {
-  const int kA[1] = {0};
-  const int kC[2] = {0, 0};
-  double rr = rhs2, rty_prev = 1.0;
+__device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit,
+                                       double rhs2, double gamma, double yty, int* iters) {
+  const int kB[1] = {0};
+  const int kC[5] = {0, 0, 0, 0, 0};
+  double rr = rhs2, beta = 0.0, ptp = yty;
   int it = 0, status = 0;
   for (;;) {
     if (!isfinite(rr)) {
@@ -659,53 +683,41 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
     }
     if (rr <= tol * tol * rhs2) break;
     if (it == maxit) break;
-    FPcgA fa;
-    fa.R = w.R;
-    fa.TI = w.TI;
-    fa.P = w.P;
-    fa.rho = rho;
-    fa.first = (it == 0);
-    fa.beta = it == 0 ? 0.0 : rty / rty_prev;
-    run_A(cx, op, fa, kA, w.partA);
-    if (team_barrier(cx.t)) {
-      status = ST_ABORTED;
-      break;
-    }
-    double pA[1];
-    reduce_items<1>(kA, w.partA, op.nA(), pA, cx.red);
-    run_B<OP>(cx, op, 0, w.partB, nullptr);
+    const int first = (it == 0);
+    op_direction(op, w, it);
+    run_B<OP>(cx, op, 0, w.partB, nullptr, beta, first);
     if (team_barrier(cx.t)) {
       status = ST_ABORTED;
       break;
     }
     double pB[1];
-    {
-      const int kb[1] = {0};
-      reduce_items<1>(kb, w.partB, op.nB(), pB, cx.red);
-    }
+    reduce_items<1>(kB, w.partB, op.nB(), pB, cx.red);
     ++it;
-    const double pq = pA[0] + pB[0];
+    const double pq = ptp + pB[0];
     if (!(pq > 0.0)) {
       status = isfinite(pq) ? ST_PCG_BREAKDOWN : ST_NONFINITE;
       break;
     }
-    FPcgC fc;
+    FPcgC2 fc;
     fc.P = w.P;
     fc.TI = w.TI;
     fc.X = w.X;
     fc.R = w.R;
     fc.rho = rho;
-    fc.alpha = rty / pq;
+    fc.alpha = gamma / pq;
+    fc.beta = beta;
+    fc.first = first;
     run_C(cx, op, fc, kC, w.partC);
     if (team_barrier(cx.t)) {
       status = ST_ABORTED;
       break;
     }
-    double pC[2];
-    reduce_items<2>(kC, w.partC, op.nC(), pC, cx.red);
-    rty_prev = rty;
-    rty = pC[0];
+    double pC[5];
+    reduce_items<5>(kC, w.partC, op.nC(), pC, cx.red);
+    beta = pC[0] / gamma;
+    gamma = pC[0];
     rr = pC[1];
+    ptp = pC[2] + 2.0 * beta * pC[3] + beta * beta * pC[4];
   }
   *iters = it;
   return status;
@@ -715,7 +727,7 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
 // mode/aP/aD) or at the trial point: computes the gap terms and the Newton
 // right-hand side for sigma (and mu = z^T s/(2n) at that point).
 struct ResOut {
-  double sumz, zs, rb2, brb, ginf, rhs2, rty;
+  double sumz, zs, rb2, brb, ginf, rhs2, rty, yty;
   int status;
 };
 
@@ -772,17 +784,18 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
   fc.aD = aD;
   fc.rho = rho;
   fc.trial = trial;
-  const int kC[3] = {1, 0, 0};
+  const int kC[4] = {1, 0, 0, 0};
   run_C(cx, op, fc, kC, w.partC);
   if (team_barrier(cx.t)) {
     o.status = ST_ABORTED;
     return o;
   }
-  double pC[3];
-  reduce_items<3>(kC, w.partC, op.nC(), pC, cx.red);
+  double pC[4];
+  reduce_items<4>(kC, w.partC, op.nC(), pC, cx.red);
   o.ginf = pC[0];
   o.rhs2 = pC[1];
   o.rty = pC[2];
+  o.yty = pC[3];
   return o;
 }
 
@@ -841,7 +854,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
         break;
       }
       int its = 0;
-      st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, &its);
+      st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, ro.yty, &its);
       pcg_total += its;
       nmat += 2 * its;
       if (st) {
@@ -876,7 +889,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
           status = rc.status;
           break;
         }
-        st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, &its);
+        st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, rc.yty, &its);
         pcg_total += its;
         nmat += 2 * its;
         if (st) {
@@ -976,12 +989,12 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
     fi.R = w.R;
     fi.X = w.X;
     fi.rho = rho;
-    const int kI[2] = {0, 0};
-    run_E(cx, n, fi, kI, w.partS);
+    const int kI[3] = {0, 0, 0};
+    run_A(cx, op, fi, kI, w.partA);
     if (team_barrier(cx.t)) st = ST_ABORTED;
-    double pI[2];
-    reduce_items<2>(kI, w.partS, nE(n), pI, cx.red);
-    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[0], pI[1], &its);
+    double pI[3];
+    reduce_items<3>(kI, w.partA, op.nA(), pI, cx.red);
+    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its);
     status = st;
     if (!st || st == ST_PCG_BREAKDOWN) {
       FBwdGather fg;

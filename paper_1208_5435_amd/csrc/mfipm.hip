@@ -124,11 +124,14 @@ TeamLayout team_layout(int op_kind, long long n, long long m, int pt_chunks) {
     take(L.Yv, (size_t)m * sizeof(double));
     L.pt_chunks = n <= DN_FUSED_MAXN ? pt_chunks : 0;
     take(L.PT, (size_t)L.pt_chunks * (size_t)n * sizeof(double));
-    L.Y1 = L.Y2 = L.mask = L.bt = L.XS = 0;
+    take(L.Dp0, (size_t)n * sizeof(double));  // previous/current direction,
+    take(L.Dp1, (size_t)n * sizeof(double));  // alternating per PCG iteration
+    L.Y1 = L.Y1p = L.Y2 = L.mask = L.bt = L.XS = 0;
   } else {
-    L.D = L.Yv = L.PT = 0;
+    L.D = L.Yv = L.PT = L.Dp0 = L.Dp1 = 0;
     L.pt_chunks = 0;
     take(L.Y1, (size_t)n * sizeof(double));  // n/2 complex
+    take(L.Y1p, (size_t)n * sizeof(double));  // transform of the direction
     take(L.Y2, (size_t)n * sizeof(double));
     take(L.mask, (size_t)n);
     take(L.bt, (size_t)n * sizeof(double));

@@ -13,6 +13,10 @@
 //           epilogue                                                (index tiles)
 // Two-pass path (larger n): pass B = row-block GEMV y = A d -> Yv, pass C =
 // column-block GEMV^T t = A^T Yv with DN_RG row groups x 64 lanes.
+// PCG form: pass C can chain the next gather (F::CHAIN: the functor returns
+// the next vector's d value, stored to D), and pass B in HAPPLY mode combines
+// d = D (+ beta Dp_prev) on load; chunk 0 stores the combination to Dp_cur
+// for the next iteration (two alternating buffers).
 #pragma once
 #include "common.h"
 
@@ -34,6 +38,8 @@ struct OpDense {
   const double* __restrict__ b;
   double* D;
   double* Yv;
+  double* Dp_prev;  // PCG: d of the previous search direction (read)
+  double* Dp_cur;   // PCG: d of the current search direction (written by item 0)
   double* PT;  // fused: partial t, nchunk x n
   int RB;
   int fused;
@@ -69,7 +75,8 @@ struct OpDense {
   // acc[1] += sum b*y (RESID).  Mode OUT writes y to `out` and skips the
   // transposed product.
   template <int CPT>
-  __device__ __forceinline__ void passB_fused(int item, int mode, double (&acc)[2], double* out) {
+  __device__ __forceinline__ void passB_fused(int item, int mode, double (&acc)[2], double* out, double beta,
+                                              int first) {
     constexpr int KP = CPT / 2;
     const long r_begin = (long)item * chunk_rows;
     const long r_end = (r_begin + chunk_rows) < m ? (r_begin + chunk_rows) : m;
@@ -77,10 +84,19 @@ struct OpDense {
     const long npair = n >> 1;  // n is even on this path
     double2 dv[KP], tacc[KP];
     const double2* D2 = reinterpret_cast<const double2*>(D);
+    const double2* P2 = reinterpret_cast<const double2*>(Dp_prev);
+    double2* C2 = reinterpret_cast<double2*>(Dp_cur);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const long p = tid + (long)k * MF_THREADS;
       dv[k] = p < npair ? D2[p] : make_double2(0.0, 0.0);
+      if (mode == DB_HAPPLY && p < npair) {
+        if (!first) {
+          const double2 w = P2[p];
+          dv[k] = make_double2(dv[k].x + beta * w.x, dv[k].y + beta * w.y);
+        }
+        if (item == 0) C2[p] = dv[k];
+      }
       tacc[k] = make_double2(0.0, 0.0);
     }
     double* red = lds;  // [2 parities][MF_WAVES][DN_FB]
@@ -175,7 +191,8 @@ struct OpDense {
       for (int g = 1; g < DN_RG; ++g) t += red[g * 64 + col];
       typename F::In in;
       f.load(c, in);
-      f.scatter(c, t, in);
+      if constexpr (F::CHAIN) D[c] = f.scatter(c, t, in);
+      else f.scatter(c, t, in);
     }
     __syncthreads();
   }
@@ -184,14 +201,19 @@ struct OpDense {
   // y_r = A[r,:] . D for the rows of the block; mode RESID subtracts b,
   // mode OUT writes y to `out` instead of Yv.  acc[0] += sum y^2,
   // acc[1] += sum b*y (RESID).  Results valid in thread 0.
-  __device__ __forceinline__ void passB_rows(int item, int mode, double (&acc)[2], double* out) {
+  __device__ __forceinline__ void passB_rows(int item, int mode, double (&acc)[2], double* out, double beta,
+                                             int first) {
     const long r0 = (long)item * RB;
     const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
     double s[DN_RBMAX];
 #pragma unroll
     for (int r = 0; r < DN_RBMAX; ++r) s[r] = 0.0;
     for (long c = threadIdx.x; c < n; c += MF_THREADS) {
-      const double dv = D[c];
+      double dv = D[c];
+      if (mode == DB_HAPPLY) {
+        if (!first) dv += beta * Dp_prev[c];
+        if (item == 0) Dp_cur[c] = dv;
+      }
 #pragma unroll
       for (int r = 0; r < DN_RBMAX; ++r)
         if (r < nr) s[r] += A[(r0 + r) * lda + c] * dv;
@@ -244,17 +266,19 @@ struct OpDense {
       for (int g = 1; g < DN_RG; ++g) t += red[g * 64 + col];
       typename F::In in;
       f.load(c, in);
-      f.scatter(c, t, in);
+      if constexpr (F::CHAIN) D[c] = f.scatter(c, t, in);
+      else f.scatter(c, t, in);
     }
     __syncthreads();
   }
 
-  __device__ __forceinline__ void passB(int item, int mode, double (&acc)[2], double* out) {
+  __device__ __forceinline__ void passB(int item, int mode, double (&acc)[2], double* out, double beta,
+                                        int first) {
     if (fused) {
-      if (n <= (DN_CPT / 2) * MF_THREADS) passB_fused<DN_CPT / 2>(item, mode, acc, out);
-      else passB_fused<DN_CPT>(item, mode, acc, out);
+      if (n <= (DN_CPT / 2) * MF_THREADS) passB_fused<DN_CPT / 2>(item, mode, acc, out, beta, first);
+      else passB_fused<DN_CPT>(item, mode, acc, out, beta, first);
     } else {
-      passB_rows(item, mode, acc, out);
+      passB_rows(item, mode, acc, out, beta, first);
     }
   }
   template <class F>

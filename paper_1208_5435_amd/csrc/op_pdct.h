@@ -22,6 +22,11 @@
 // B = row FFT + spectral + row IFFT (items: pairs of rows k1, N1-k1),
 // C = column IFFT + scatter (items as A).  Complex intermediates live in HBM
 // in item-major tiles so that both sides of each exchange are contiguous.
+// Pass C can chain the next gather: A and C items cover the same indices, so
+// a functor that returns the next vector's d value for each index gets its
+// column FFT done in the same pass (written to Y1); pass B can then combine
+// Y1 with a stored Y1p by linearity (Y1p <- Y1 + beta Y1p) before the row
+// FFTs, so a PCG iteration needs only passes B and C.
 #pragma once
 #include "common.h"
 
@@ -170,6 +175,7 @@ struct OpPdct {
   const int* __restrict__ rows;
   const double* __restrict__ b;
   cplx* Y1;
+  cplx* Y1p;  // column-FFT data of the current search direction (PCG)
   cplx* Y2;
   unsigned char* mask;  // spectral layout, n bytes
   double* bt;           // spectral layout, n doubles
@@ -243,6 +249,11 @@ struct OpPdct {
       }
     }
     __syncthreads();
+    column_fft_store(q);
+  }
+
+  // forward column FFTs of the gathered tile, four-step twiddle, store to Y1
+  __device__ __forceinline__ void column_fft_store(int q) {
     lds_fft(tile, l1, 8, 8, 1, -1, tw, log2M());
     for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) {
       const int k1 = e >> 3, c = e & 7;
@@ -255,12 +266,14 @@ struct OpPdct {
   }
 
   // ---- pass C: Y2 -> column IFFTs -> scatter t to the functor ----
+  // (F::CHAIN: the functor returns the next d value of each index, which
+  // replaces t in the same tile slot; the tile is then column-FFT'd to Y1.)
   template <class F>
   __device__ __forceinline__ void passC(int q, F& f) {
     for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(long)q * N1 * 8 + e];
     __syncthreads();
     lds_fft(tile, l1, 8, 8, 1, +1, tw, log2M());
-    const double* td = reinterpret_cast<const double*>(tile);
+    double* td = reinterpret_cast<double*>(tile);
     const int units = 16 * N1;
     constexpr int U = PD_U;
     for (int base = 0; base < units; base += MF_THREADS * U) {
@@ -278,10 +291,14 @@ struct OpPdct {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int u = base + threadIdx.x + k * MF_THREADS;
-        if (u < units) f.scatter(idx[k], td[slot[k]], in[k]);
+        if (u < units) {
+          if constexpr (F::CHAIN) td[slot[k]] = f.scatter(idx[k], td[slot[k]], in[k]);
+          else f.scatter(idx[k], td[slot[k]], in[k]);
+        }
       }
     }
     __syncthreads();
+    if constexpr (F::CHAIN) column_fft_store(q);
   }
 
   // Spectral work for one pair of half-spectrum indices (kA, kB = H - kA).
@@ -373,7 +390,8 @@ struct OpPdct {
   }
 
   // ---- pass B: two rows of Y1 -> row FFT -> spectral -> row IFFT -> Y2 ----
-  __device__ __forceinline__ void passB(int r, int mode, double (&acc)[2]) {
+  // Mode HAPPLY combines the rows first: Y1p <- Y1 (+ beta Y1p unless first).
+  __device__ __forceinline__ void passB(int r, int mode, double (&acc)[2], double beta, int first) {
     const int k1a = r == 0 ? 0 : r;
     const int k1b = r == 0 ? (N1 >> 1) : N1 - r;
     cur_k1a = k1a;
@@ -391,7 +409,16 @@ struct OpPdct {
       const int q = u >> 3, c = u & 7;
       const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
       const int k1 = s ? k1b : k1a;
-      tile[s * N2 + j2] = Y1[((long)q * N1 + k1) * 8 + c];
+      const long gi = ((long)q * N1 + k1) * 8 + c;
+      cplx v = Y1[gi];
+      if (mode == PB_HAPPLY) {
+        if (!first) {
+          const cplx w = Y1p[gi];
+          v = mkc(v.x + beta * w.x, v.y + beta * w.y);
+        }
+        Y1p[gi] = v;
+      }
+      tile[s * N2 + j2] = v;
     }
     __syncthreads();
     lds_fft(tile, l2, 2, 1, N2, -1, tw, log2M());
