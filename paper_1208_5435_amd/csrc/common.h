@@ -48,14 +48,14 @@ struct Twiddle {
   const cplx* hi;
   int lo_bits;
   int scale_shift;
-  __device__ __forceinline__ cplx get(long e) const {
+  __device__ __forceinline__ cplx get(int e) const {  // e < 2^22
     e <<= scale_shift;
     cplx a = hi[e >> lo_bits];
-    cplx b = lo[e & ((1L << lo_bits) - 1)];
+    cplx b = lo[e & ((1 << lo_bits) - 1)];
     return cmul(a, b);
   }
   // exp(sign * 2 pi i e / M)
-  __device__ __forceinline__ cplx get(long e, int sign) const {
+  __device__ __forceinline__ cplx get(int e, int sign) const {
     cplx t = get(e);
     return sign < 0 ? t : cconj(t);
   }

@@ -76,32 +76,53 @@ __device__ __forceinline__ void dft_small<8>(cplx (&v)[8], int sign) {
   }
 }
 
-// One Stockham (self-sorting) radix-R pass over `count` independent
-// sequences of length L held in LDS, in place: every thread first loads all
-// its butterfly inputs to registers, the workgroup synchronises, then the
-// outputs are written.  Element (s, i) is at buf[s * sstride + i * istride].
-// log2M: log2 of the twiddle resolution of the instance (4 n).
+// Twiddles and butterfly of one Stockham (self-sorting) radix-R step:
+// butterfly b of a sequence at stage Ls takes elements b + r L/R and writes
+// (b / Ls) Ls R + (b mod Ls) + r Ls, its inputs rotated by powers of
+// w = exp(sign 2 pi i (b mod Ls) / (Ls R)).  All sizes are powers of two and
+// passed as log2.  twsh = log2M - log2(Ls R), log2M being the log2 of the
+// twiddle resolution of the instance (4 n).
 template <int R>
-__device__ __forceinline__ void stockham_pass(cplx* buf, int L, int Ls, int count, int istride, int sstride, int sign,
-                              const Twiddle& tw, int log2M, int log2LsR) {
+__device__ __forceinline__ void stockham_bfly(cplx (&v)[R], int j, int twsh, int sign, const Twiddle& tw) {
+  if (j != 0) {
+    const cplx w1 = tw.get(j << twsh, sign);
+    cplx w = w1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      v[r] = cmul(v[r], w);
+      if (r + 1 < R) w = cmul(w, w1);
+    }
+  }
+  dft_small<R>(v, sign);
+}
+
+// One radix-R pass over 2^lcount sequences of length 2^lL in LDS, in place,
+// spread over the whole workgroup: every thread loads its butterfly inputs,
+// the workgroup synchronises, then the outputs are written.  Element (s, i)
+// is at buf[(s << lss) + (i << lis)].
+template <int R, int LR>
+__device__ __forceinline__ void stockham_pass(cplx* buf, int lL, int lLs, int lcount, int lis, int lss, int sign,
+                                              const Twiddle& tw, int log2M) {
   constexpr int NB = PD_EPT / R;
-  const int nbper = L / R;
-  const int nb = nbper * count;
+  const int lnb = lL - LR;  // log2 butterflies per sequence
+  const int nb = 1 << (lnb + lcount);
+  const int twsh = log2M - (lLs + LR);
   cplx v[NB][R];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     const int bt = threadIdx.x + k * MF_THREADS;
     if (bt < nb) {
       int s, b;
-      if (istride == 1) {
-        s = bt / nbper;
-        b = bt - s * nbper;
+      if (lis == 0) {
+        s = bt >> lnb;
+        b = bt & ((1 << lnb) - 1);
       } else {
-        s = bt % count;
-        b = bt / count;
+        s = bt & ((1 << lcount) - 1);
+        b = bt >> lcount;
       }
+      const int base = (s << lss) + (b << lis);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = buf[s * sstride + (b + r * nbper) * istride];
+      for (int r = 0; r < R; ++r) v[k][r] = buf[base + ((r << lnb) << lis)];
     }
   }
   __syncthreads();
@@ -110,56 +131,43 @@ __device__ __forceinline__ void stockham_pass(cplx* buf, int L, int Ls, int coun
     const int bt = threadIdx.x + k * MF_THREADS;
     if (bt < nb) {
       int s, b;
-      if (istride == 1) {
-        s = bt / nbper;
-        b = bt - s * nbper;
+      if (lis == 0) {
+        s = bt >> lnb;
+        b = bt & ((1 << lnb) - 1);
       } else {
-        s = bt % count;
-        b = bt / count;
+        s = bt & ((1 << lcount) - 1);
+        b = bt >> lcount;
       }
-      const int j = b & (Ls - 1);
-      const int kk = b / Ls;
-      if (j != 0) {
-        // w1 = exp(sign * 2 pi i j / (Ls R)), powers by repeated products
-        const cplx w1 = tw.get((long)j << (log2M - log2LsR), sign);
-        cplx w = w1;
+      const int j = b & ((1 << lLs) - 1);
+      stockham_bfly<R>(v[k], j, twsh, sign, tw);
+      const int ob = (s << lss) + ((((b >> lLs) << (lLs + LR)) + j) << lis);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[k][r] = cmul(v[k][r], w);
-          if (r + 1 < R) w = cmul(w, w1);
-        }
-      }
-      dft_small<R>(v[k], sign);
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[s * sstride + (kk * Ls * R + j + r * Ls) * istride] = v[k][r];
+      for (int r = 0; r < R; ++r) buf[ob + ((r << lLs) << lis)] = v[k][r];
     }
   }
   __syncthreads();
 }
 
-// Unnormalised DFT (sign -1) or inverse DFT (sign +1) of `count` sequences of
-// length L = 2^log2L (count * L <= 4096).  Caller synchronises before.
-// Radix 8 while at least three factors of two remain, then 4 or 2: the
-// fewest passes (each pass costs two workgroup barriers and an LDS round trip,
-// which outweighs idle lanes on small tiles).
-__device__ __forceinline__ void lds_fft(cplx* buf, int log2L, int count, int istride, int sstride, int sign,
-                               const Twiddle& tw, int log2M) {
-  const int L = 1 << log2L;
-  int Ls = 1, lg = 0;
-  while (Ls < L) {
-    int rem = log2L - lg;
-    if (rem > 3) rem = 3;
-    if (rem == 3) {
-      stockham_pass<8>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 3);
-      Ls <<= 3;
+// Unnormalised DFT (sign -1) or inverse DFT (sign +1) of 2^lcount sequences
+// of length 2^lL held in LDS (element (s, i) at buf[(s << lss) + (i << lis)],
+// 2^(lcount + lL) <= 4096).  Caller synchronises before; the result is visible
+// to the whole workgroup on return.  Radix 8 while at least three factors of
+// two remain, then 4 or 2: the fewest passes (each pass costs two workgroup
+// barriers and an LDS round trip, which outweighs idle lanes on small tiles).
+// Index arithmetic is shifts and masks only (no integer division).
+__device__ __forceinline__ void lds_fft(cplx* buf, int lL, int lcount, int lis, int lss, int sign,
+                                        const Twiddle& tw, int log2M) {
+  int lg = 0;
+  while (lg < lL) {
+    const int rem = lL - lg;
+    if (rem >= 3) {
+      stockham_pass<8, 3>(buf, lL, lg, lcount, lis, lss, sign, tw, log2M);
       lg += 3;
     } else if (rem == 2) {
-      stockham_pass<4>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 2);
-      Ls <<= 2;
+      stockham_pass<4, 2>(buf, lL, lg, lcount, lis, lss, sign, tw, log2M);
       lg += 2;
     } else {
-      stockham_pass<2>(buf, L, Ls, count, istride, sstride, sign, tw, log2M, lg + 1);
-      Ls <<= 1;
+      stockham_pass<2, 1>(buf, lL, lg, lcount, lis, lss, sign, tw, log2M);
       lg += 1;
     }
   }
@@ -187,9 +195,9 @@ struct OpPdct {
   double a0, a1;
 
   // mask value of coefficient owner (k, e), from the LDS copy of the item
-  __device__ __forceinline__ double mval(long k, int e) const {
-    const int k1 = (int)(k & (N1 - 1));
-    return (double)msk[(k1 == cur_k1a ? 0 : 2 * N2) + (int)((k >> l1) << 1) + e];
+  __device__ __forceinline__ double mval(int k, int e) const {
+    const int k1 = k & (N1 - 1);
+    return (double)msk[(k1 == cur_k1a ? 0 : 2 * N2) + ((k >> l1) << 1) + e];
   }
 
   __device__ int nA() const { return N2 >> 3; }
@@ -198,15 +206,15 @@ struct OpPdct {
   __device__ int log2M() const { return logn + 2; }
 
   // position of coefficient-owner (half index k, e) in the spectral layout
-  __device__ __forceinline__ long spos(long k, int e) const {
-    return (((k & (N1 - 1)) * (long)N2 + (k >> l1)) << 1) + e;
+  __device__ __forceinline__ int spos(int k, int e) const {
+    return ((((k & (N1 - 1)) << l2) + (k >> l1)) << 1) + e;
   }
   // spectral-layout position of DCT coefficient index kk in [0, n)
   __device__ __forceinline__ long coef_pos(long kk) const {
     if (kk == 0) return spos(0, 0);
     if (kk == H) return spos(0, 1);
-    if (kk < H) return spos(kk, 0);
-    return spos(n - kk, 1);
+    if (kk < H) return spos((int)kk, 0);
+    return spos((int)(n - kk), 1);
   }
 
   // Unit u in [0, 16 N1) of a column-block-pair item q -> d index and the
@@ -217,7 +225,7 @@ struct OpPdct {
     const int j2 = seg == 0 ? 4 * q + cc : N2 - 4 - 4 * q + cc;
     const int colA = seg == 0 ? cc : 4 + (3 - cc);
     const int colM = seg == 0 ? 4 + cc : 3 - cc;
-    i = 4L * ((long)j1 * N2 + j2) + e;
+    i = (long)((((j1 << l2) + j2) << 2) + e);
     if (e == 0) slot = (j1 * 8 + colA) * 2;
     else if (e == 2) slot = (j1 * 8 + colA) * 2 + 1;
     else if (e == 3) slot = ((N1 - 1 - j1) * 8 + colM) * 2;
@@ -254,13 +262,13 @@ struct OpPdct {
 
   // forward column FFTs of the gathered tile, four-step twiddle, store to Y1
   __device__ __forceinline__ void column_fft_store(int q) {
-    lds_fft(tile, l1, 8, 8, 1, -1, tw, log2M());
+    lds_fft(tile, l1, 3, 3, 0, -1, tw, log2M());
     for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) {
       const int k1 = e >> 3, c = e & 7;
       const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
       cplx v = tile[e];
-      v = cmul(v, tw.get(8L * ((long)j2 * k1), -1));
-      Y1[(long)q * N1 * 8 + e] = v;
+      v = cmul(v, tw.get((j2 * k1) << 3, -1));
+      Y1[(q << (l1 + 3)) + e] = v;
     }
     __syncthreads();
   }
@@ -270,9 +278,9 @@ struct OpPdct {
   // replaces t in the same tile slot; the tile is then column-FFT'd to Y1.)
   template <class F>
   __device__ __forceinline__ void passC(int q, F& f) {
-    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(long)q * N1 * 8 + e];
+    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(q << (l1 + 3)) + e];
     __syncthreads();
-    lds_fft(tile, l1, 8, 8, 1, +1, tw, log2M());
+    lds_fft(tile, l1, 3, 3, 0, +1, tw, log2M());
     double* td = reinterpret_cast<double*>(tile);
     const int units = 16 * N1;
     constexpr int U = PD_U;
@@ -303,14 +311,14 @@ struct OpPdct {
 
   // Spectral work for one pair of half-spectrum indices (kA, kB = H - kA).
   // acc[0] += sum of squared outputs, acc[1] += sum b~ * output.
-  __device__ __forceinline__ void spectral_pair(int mode, long kA, int pA, long kB, int pB, double (&acc)[2]) {
+  __device__ __forceinline__ void spectral_pair(int mode, int kA, int pA, int kB, int pB, double (&acc)[2]) {
     const cplx WA = tile[pA];
     const double h = 0.70710678118654752440;
     if (kA == 0) {
       // V_0 = Re W0 + Im W0, V_H = Re W0 - Im W0 (both real)
       const double V0 = WA.x + WA.y, VH = WA.x - WA.y;
       double X0 = a0 * V0, XH = a1 * VH * h;
-      const long p0 = spos(0, 0), p1 = spos(0, 1);
+      const int p0 = spos(0, 0), p1 = spos(0, 1);
       if (mode == PB_FWDOUT) {
         XS[p0] = X0;
         XS[p1] = XH;
@@ -340,7 +348,7 @@ struct OpPdct {
     const cplx VB = cadd(cconj(E), cmul(tw.get(4 * kB), cconj(O)));
     const cplx UB = cmul(tw.get(kB), VB);
     // coefficients owned: e=0 -> X_k = a1 Re U, e=1 -> X_{n-k} = -a1 Im U
-    const long qa0 = spos(kA, 0), qa1 = qa0 + 1, qb0 = spos(kB, 0), qb1 = qb0 + 1;
+    const int qa0 = spos(kA, 0), qa1 = qa0 + 1, qb0 = spos(kB, 0), qb1 = qb0 + 1;
     double xa0 = a1 * UA.x, xa1 = -a1 * UA.y, xb0 = a1 * UB.x, xb1 = -a1 * UB.y;
     const bool self = (kA == kB);
     if (mode == PB_FWDOUT) {
@@ -397,8 +405,8 @@ struct OpPdct {
     cur_k1a = k1a;
     if (mode != PB_FWDOUT) {
       // the item's mask bytes (two rows of 2 N2) to LDS, as 32-bit words
-      const unsigned* ga = reinterpret_cast<const unsigned*>(mask + (long)k1a * 2 * N2);
-      const unsigned* gb = reinterpret_cast<const unsigned*>(mask + (long)k1b * 2 * N2);
+      const unsigned* ga = reinterpret_cast<const unsigned*>(mask + (k1a << (l2 + 1)));
+      const unsigned* gb = reinterpret_cast<const unsigned*>(mask + (k1b << (l2 + 1)));
       unsigned* ml = reinterpret_cast<unsigned*>(msk);
       const int wpr = N2 >> 1;  // 32-bit words per row
       for (int i = threadIdx.x; i < 2 * wpr; i += MF_THREADS) ml[i] = i < wpr ? ga[i] : gb[i - wpr];
@@ -409,7 +417,7 @@ struct OpPdct {
       const int q = u >> 3, c = u & 7;
       const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
       const int k1 = s ? k1b : k1a;
-      const long gi = ((long)q * N1 + k1) * 8 + c;
+      const int gi = (((q << l1) + k1) << 3) + c;
       cplx v = Y1[gi];
       if (mode == PB_HAPPLY) {
         if (!first) {
@@ -421,29 +429,29 @@ struct OpPdct {
       tile[s * N2 + j2] = v;
     }
     __syncthreads();
-    lds_fft(tile, l2, 2, 1, N2, -1, tw, log2M());
+    lds_fft(tile, l2, 1, 0, l2, -1, tw, log2M());
     if (r != 0) {
       for (int u = threadIdx.x; u < N2; u += MF_THREADS) {
-        const long kA = k1a + (long)N1 * u;
-        const long kB = k1b + (long)N1 * (N2 - 1 - u);
+        const int kA = k1a + (u << l1);
+        const int kB = k1b + ((N2 - 1 - u) << l1);
         spectral_pair(mode, kA, u, kB, N2 + (N2 - 1 - u), acc);
       }
     } else {
       for (int u = threadIdx.x; u < N2 + 1; u += MF_THREADS) {
         if (u <= (N2 >> 1)) {
           const int pb = (N2 - u) & (N2 - 1);
-          spectral_pair(mode, (long)N1 * u, u, (long)N1 * pb, pb, acc);
+          spectral_pair(mode, u << l1, u, pb << l1, pb, acc);
         } else {
           const int v = u - (N2 >> 1) - 1;
-          const long kA = (N1 >> 1) + (long)N1 * v;
-          const long kB = (N1 >> 1) + (long)N1 * (N2 - 1 - v);
+          const int kA = (N1 >> 1) + (v << l1);
+          const int kB = (N1 >> 1) + ((N2 - 1 - v) << l1);
           spectral_pair(mode, kA, N2 + v, kB, N2 + (N2 - 1 - v), acc);
         }
       }
     }
     __syncthreads();
     if (mode == PB_FWDOUT) return;
-    lds_fft(tile, l2, 2, 1, N2, +1, tw, log2M());
+    lds_fft(tile, l2, 1, 0, l2, +1, tw, log2M());
     for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
       const int s = u2 >= N2;
       const int u = u2 - s * N2;
@@ -451,8 +459,8 @@ struct OpPdct {
       const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
       const int k1 = s ? k1b : k1a;
       cplx v = tile[s * N2 + j2];
-      v = cmul(v, tw.get(8L * ((long)j2 * k1), +1));
-      Y2[((long)q * N1 + k1) * 8 + c] = v;
+      v = cmul(v, tw.get((j2 * k1) << 3, +1));
+      Y2[(((q << l1) + k1) << 3) + c] = v;
     }
     __syncthreads();
   }
