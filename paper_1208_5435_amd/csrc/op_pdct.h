@@ -278,22 +278,34 @@ struct OpPdct {
   // replaces t in the same tile slot; the tile is then column-FFT'd to Y1.)
   template <class F>
   __device__ __forceinline__ void passC(int q, F& f) {
+    const int units = 16 * N1;
+    constexpr int U = PD_U;
+    // The functor's inputs of the first batch of units are requested before
+    // the column IFFTs so that their memory latency overlaps the transform.
+    typename F::In in[U];
+    long idx[U];
+    int slot[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int u = threadIdx.x + k * MF_THREADS;
+      if (u < units) {
+        unit_map(q, u, idx[k], slot[k]);
+        f.load(idx[k], in[k]);
+      }
+    }
     for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(q << (l1 + 3)) + e];
     __syncthreads();
     lds_fft(tile, l1, 3, 3, 0, +1, tw, log2M());
     double* td = reinterpret_cast<double*>(tile);
-    const int units = 16 * N1;
-    constexpr int U = PD_U;
     for (int base = 0; base < units; base += MF_THREADS * U) {
-      typename F::In in[U];
-      long idx[U];
-      int slot[U];
+      if (base > 0) {
 #pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const int u = base + threadIdx.x + k * MF_THREADS;
-        if (u < units) {
-          unit_map(q, u, idx[k], slot[k]);
-          f.load(idx[k], in[k]);
+        for (int k = 0; k < U; ++k) {
+          const int u = base + threadIdx.x + k * MF_THREADS;
+          if (u < units) {
+            unit_map(q, u, idx[k], slot[k]);
+            f.load(idx[k], in[k]);
+          }
         }
       }
 #pragma unroll
