@@ -65,19 +65,30 @@ struct Twiddle {
 // Teams: groups of workgroups that cooperate on one instance.  Every
 // workgroup of a team passes the same sequence of barriers because all
 // control decisions are taken from identical, deterministically reduced
-// values.  The barrier is two-level: workgroups arrive on the counter of
-// their group of MF_BAR_GS; the last arrival of a group arrives on the top
-// counter; the last top arrival publishes the generation in a release word on
-// which everyone waits.  Counters only grow (targets are generation * count),
-// so nothing is reset between barriers.  The wait is bounded in wall-clock
-// time: past the bound a global abort flag is raised, later barriers return at
-// once and the solver loops stop, so the grid always drains.
+// values.
 //
-// Control block layout (unsigned long long words, 128-byte lines):
-//   [0] release word, [16] top counter, [32 + 16 g] counter of group g.
+// The barrier is two-level and follows the chip's cache structure: the
+// workgroups of a team that run on one XCD (accelerator complex die, one L2
+// each) form a group.  A workgroup waits until its own global stores are
+// complete in its XCD's L2 and arrives on its group's counter; the group's
+// last arrival writes that L2 back once for the whole group (agent-scope
+// release) and arrives on the top counter; the last top arrival publishes the
+// generation in a release word on which everyone waits, then acquires
+// (invalidating its L2 and L1 view).  One write-back per XCD instead of one
+// per workgroup is what makes the release side cheap.  Counters only grow
+// (targets are generation * count), so nothing is reset between barriers.
+// Every wait is bounded in wall-clock time: past the bound a global abort flag
+// is raised, later barriers return at once and the solver loops stop, so the
+// grid always drains.
+//
+// Control block layout (unsigned long long words):
+//   [0] release word, [16] top counter, [32 + 16 x] counter of the group on
+//   XCD x (x < 16), [MF_CTL_REG_WORD + x] registration count of XCD x,
+//   [MF_CTL_REG_WORD + 16] registration total.
 // ---------------------------------------------------------------------------
-#define MF_BAR_GS 16
-#define MF_BAR_MAXGROUPS 64
+#define MF_MAX_XCD 16
+#define MF_MAX_TEAM 1024  // largest team (workgroups per instance)
+#define MF_CTL_REG_WORD 1296     // registration counters (one-time, after the group counters)
 #define MF_CTL_SLOT_BYTES 10240  // byte offset of the queue slot in a team control block
 #define MF_CTL_ERR_BYTES 10304   // byte offset of the input-check flag
 #define MF_CTL_BYTES 12288       // bytes of one team control block
@@ -90,59 +101,85 @@ struct Team {
   unsigned long long gen;
   int* abort_flag;
   unsigned long long spin_ticks;  // bound on one wait, in wall-clock ticks
+  int xcd;                        // XCD this workgroup runs on
+  int gsize;                      // workgroups of the team on that XCD
+  int ngroups;                    // XCDs the team occupies
 };
 
 __device__ __forceinline__ int ld_flag(int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Hardware id of the XCD executing this wave (HW_REG_XCC_ID, bits 3:0).
+__device__ __forceinline__ int hw_xcd_id() { return __builtin_amdgcn_s_getreg((15 << 11) | 20) & (MF_MAX_XCD - 1); }
+
+// Spins (thread 0) until *p >= target; returns nonzero on abort or timeout.
+__device__ __forceinline__ int spin_ge(unsigned long long* p, unsigned long long target, Team& t) {
+  const unsigned long long t0 = wall_clock64();
+  unsigned iter = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++iter & 255u) == 0) {
+      if (ld_flag(t.abort_flag)) return 1;
+      if (wall_clock64() - t0 > t.spin_ticks) {
+        __hip_atomic_store(t.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 1;
+      }
+    }
+  }
+  return 0;
+}
+
+// One-time set-up of the barrier groups: every workgroup registers its XCD,
+// waits for the whole team, then reads its group's size and the number of
+// groups.  Returns nonzero if the run was aborted.
+__device__ __forceinline__ int team_init(Team& t) {
+  __shared__ int s_init[3];
+  t.gen = 0;
+  t.xcd = hw_xcd_id();
+  if (threadIdx.x == 0) {
+    unsigned long long* reg = t.ctl + MF_CTL_REG_WORD;
+    __hip_atomic_fetch_add(reg + t.xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    __hip_atomic_fetch_add(reg + MF_MAX_XCD, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ab = spin_ge(reg + MF_MAX_XCD, (unsigned long long)t.size, t);
+    int ng = 0;
+    for (int x = 0; x < MF_MAX_XCD; ++x)
+      ng += __hip_atomic_load(reg + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
+    s_init[0] = ab;
+    s_init[1] = (int)__hip_atomic_load(reg + t.xcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_init[2] = ng;
+  }
+  __syncthreads();
+  const int ab = s_init[0];
+  t.gsize = s_init[1];
+  t.ngroups = s_init[2];
+  __syncthreads();
+  return ab;
+}
+
 // Returns nonzero if the run was aborted.
 __device__ __forceinline__ int team_barrier(Team& t) {
   __shared__ int s_abort;
   // Every wave waits until its own global stores are complete in L2 before
-  // the workgroup barrier; thread 0's agent-scope release (L2 write-back)
-  // below then covers the stores of all waves of the workgroup.
+  // the workgroup barrier, so the group's write-back below covers them.
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   t.gen += 1;
   if (threadIdx.x == 0) {
     int ab = ld_flag(t.abort_flag);
     unsigned long long* rel = t.ctl;
-    const int g = t.rank / MF_BAR_GS;
-    const int ngroups = (t.size + MF_BAR_GS - 1) / MF_BAR_GS;
-    const int gcount = min(MF_BAR_GS, t.size - g * MF_BAR_GS);
-    // release this workgroup's writes, then arrive
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned long long old =
-        __hip_atomic_fetch_add(t.ctl + 32 + 16 * g, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 == t.gen * (unsigned long long)gcount) {
-      // last of the group: acquire the group's writes, release them onward
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_fetch_add(t.ctl + 32 + 16 * t.xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == t.gen * (unsigned long long)t.gsize) {
+      // last of this XCD's group: every member's stores are in this L2
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned long long old2 =
           __hip_atomic_fetch_add(t.ctl + 16, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old2 + 1 == t.gen * (unsigned long long)ngroups) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (old2 + 1 == t.gen * (unsigned long long)t.ngroups)
         __hip_atomic_store(rel, t.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
     }
-    if (!ab) {
-      const unsigned long long t0 = wall_clock64();
-      unsigned iter = 0;
-      while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < t.gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++iter & 255u) == 0) {
-          if (ld_flag(t.abort_flag)) {
-            ab = 1;
-            break;
-          }
-          if (wall_clock64() - t0 > t.spin_ticks) {
-            __hip_atomic_store(t.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ab = 1;
-            break;
-          }
-        }
-      }
-    }
+    if (!ab) ab = spin_ge(rel, t.gen, t);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_abort = ab;
   }

@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
   cx.t.spin_ticks = a.spin_ticks;
   const TeamWS w = make_ws(a, cx.t.id);
   cx.t.ctl = w.bar;
+  if (team_init(cx.t)) return;
   for (;;) {
     // the previous slot value has been read by every workgroup of the team
     if (team_barrier(cx.t)) break;
@@ -338,7 +339,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     const int total = h->req_wg > 0 ? std::min(h->req_wg, gmax) : gmax;
     num_teams = std::max(1, std::min(P.batch, total / team_size));
   }
-  if (team_size > MF_BAR_GS * MF_BAR_MAXGROUPS) team_size = MF_BAR_GS * MF_BAR_MAXGROUPS;
+  if (team_size > MF_MAX_TEAM) team_size = MF_MAX_TEAM;
   const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch);
   if (num_teams > teams_bound) num_teams = teams_bound;
   if (h->scratch_lane[P.op_kind][bwd] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
