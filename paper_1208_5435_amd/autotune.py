@@ -72,16 +72,16 @@ def candidates(op_kind: int, n_max: int, m_max: int, batch: int, num_cu: int = 2
         if op_kind == 1:  # partial DCT
             lh = int(math.log2(n_max)) - 1
             base = lh // 2
-            tiles = sorted({t for t in (base - 1, base, base + 1) if 1 <= t <= 9 and 3 <= lh - t <= 11})
-            for wg in (0, 32, 64, 128, 256):
+            tiles = sorted({t for t in (base - 2, base - 1, base, base + 1) if 1 <= t <= 9 and 3 <= lh - t <= 11})
+            for wg in (0, 32, 64, 96, 128, 192, 256):
                 for t in tiles:
                     out.append((wg, 0, t))
         else:
             for wg in (0, 16, 32, 64, 128, 256):
                 out.append((wg, 0, 0))
     else:
-        for ts in (1, 2, 4, 8, 16, 32):
-            if ts * min(batch, num_cu) >= 1:
+        for ts in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+            if ts <= num_cu:
                 out.append((0, ts, 0))
     return out
 
