@@ -563,7 +563,7 @@ __device__ __forceinline__ int ilog2(long v) {
 }
 
 __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds,
-                                        int) {
+                                        int team_size) {
   op.n = d.n;
   op.m = d.m;
   op.H = (int)(d.n >> 1);
@@ -578,6 +578,8 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.l2 = lh - l1;
   op.N1 = 1 << op.l1;
   op.N2 = 1 << op.l2;
+  // narrower pass-A/C items when blocks of 8 columns would leave workgroups idle
+  op.lcb = (op.N2 >> 3) < team_size ? 2 : 3;
   op.rows = a.rows + (a.shared_op ? 0 : d.m_off);
   op.b = a.b ? a.b + d.m_off : nullptr;
   op.Y1 = w.Y1;

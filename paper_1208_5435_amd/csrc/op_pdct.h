@@ -180,6 +180,7 @@ struct OpPdct {
   long n;
   long m;
   int H, N1, N2, l1, l2, logn;
+  int lcb;  // log2 of the columns of a pass-A/C item: 3 (two mirrored blocks of 4) or 2 (of 2)
   const int* __restrict__ rows;
   const double* __restrict__ b;
   cplx* Y1;
@@ -200,9 +201,14 @@ struct OpPdct {
     return (double)msk[(k1 == cur_k1a ? 0 : 2 * N2) + ((k >> l1) << 1) + e];
   }
 
-  __device__ int nA() const { return N2 >> 3; }
+  __device__ int nA() const { return N2 >> lcb; }
   __device__ int nB() const { return N1 >> 1; }
-  __device__ int nC() const { return N2 >> 3; }
+  __device__ int nC() const { return N2 >> lcb; }
+  // tile column c of item q -> column j2 of the N1 x N2 grid
+  __device__ __forceinline__ int col_j2(int q, int c) const {
+    const int hb = 1 << (lcb - 1);
+    return c < hb ? (q << (lcb - 1)) + c : N2 - 1 - (q << (lcb - 1)) - (c - hb);
+  }
   __device__ int log2M() const { return logn + 2; }
 
   // position of coefficient-owner (half index k, e) in the spectral layout
@@ -217,26 +223,31 @@ struct OpPdct {
     return spos((int)(n - kk), 1);
   }
 
-  // Unit u in [0, 16 N1) of a column-block-pair item q -> d index and the
-  // tile slot (double offset into the LDS tile viewed as doubles).
+  // An item q holds 2^lcb grid columns: the block of hb = 2^(lcb-1) columns
+  // starting at hb q and its mirror image ending at N2 - 1 - hb q, so that
+  // w_j and w_{H-1-j} of the gather (mirrored row and column) meet in one
+  // item.  Unit u in [0, N1 2^(lcb+1)) -> d index and the tile slot (double
+  // offset into the LDS tile viewed as doubles, [row][column][re, im]).
+  __device__ __forceinline__ int units() const { return N1 << (lcb + 1); }
   __device__ __forceinline__ void unit_map(int q, int u, long& i, int& slot) const {
-    const int j1 = u >> 5, w = u & 31, seg = w >> 4, off = w & 15;
+    const int hb = 1 << (lcb - 1);
+    const int j1 = u >> (lcb + 2), w = u & ((4 << lcb) - 1), seg = w >> (lcb + 1), off = w & ((2 << lcb) - 1);
     const int cc = off >> 2, e = off & 3;
-    const int j2 = seg == 0 ? 4 * q + cc : N2 - 4 - 4 * q + cc;
-    const int colA = seg == 0 ? cc : 4 + (3 - cc);
-    const int colM = seg == 0 ? 4 + cc : 3 - cc;
+    const int j2 = seg == 0 ? (q << (lcb - 1)) + cc : N2 - hb - (q << (lcb - 1)) + cc;
+    const int colA = seg == 0 ? cc : hb + (hb - 1 - cc);
+    const int colM = seg == 0 ? hb + cc : hb - 1 - cc;
     i = (long)((((j1 << l2) + j2) << 2) + e);
-    if (e == 0) slot = (j1 * 8 + colA) * 2;
-    else if (e == 2) slot = (j1 * 8 + colA) * 2 + 1;
-    else if (e == 3) slot = ((N1 - 1 - j1) * 8 + colM) * 2;
-    else slot = ((N1 - 1 - j1) * 8 + colM) * 2 + 1;
+    if (e == 0) slot = (((j1 << lcb) + colA) << 1);
+    else if (e == 2) slot = (((j1 << lcb) + colA) << 1) + 1;
+    else if (e == 3) slot = ((((N1 - 1 - j1) << lcb) + colM) << 1);
+    else slot = ((((N1 - 1 - j1) << lcb) + colM) << 1) + 1;
   }
 
   // ---- pass A: gather d (from the functor) + column FFTs + twiddle -> Y1 ----
   template <class F>
   __device__ __forceinline__ void passA(int q, F& f) {
     double* td = reinterpret_cast<double*>(tile);
-    const int units = 16 * N1;
+    const int units = this->units();
     constexpr int U = PD_U;
     for (int base = 0; base < units; base += MF_THREADS * U) {
       typename F::In in[U];
@@ -262,13 +273,13 @@ struct OpPdct {
 
   // forward column FFTs of the gathered tile, four-step twiddle, store to Y1
   __device__ __forceinline__ void column_fft_store(int q) {
-    lds_fft(tile, l1, 3, 3, 0, -1, tw, log2M());
-    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) {
-      const int k1 = e >> 3, c = e & 7;
-      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+    lds_fft(tile, l1, lcb, lcb, 0, -1, tw, log2M());
+    for (int e = threadIdx.x; e < (N1 << lcb); e += MF_THREADS) {
+      const int k1 = e >> lcb, c = e & ((1 << lcb) - 1);
+      const int j2 = col_j2(q, c);
       cplx v = tile[e];
       v = cmul(v, tw.get((j2 * k1) << 3, -1));
-      Y1[(q << (l1 + 3)) + e] = v;
+      Y1[(q << (l1 + lcb)) + e] = v;
     }
     __syncthreads();
   }
@@ -278,7 +289,7 @@ struct OpPdct {
   // replaces t in the same tile slot; the tile is then column-FFT'd to Y1.)
   template <class F>
   __device__ __forceinline__ void passC(int q, F& f) {
-    const int units = 16 * N1;
+    const int units = this->units();
     constexpr int U = PD_U;
     // The functor's inputs of the first batch of units are requested before
     // the column IFFTs so that their memory latency overlaps the transform.
@@ -293,9 +304,9 @@ struct OpPdct {
         f.load(idx[k], in[k]);
       }
     }
-    for (int e = threadIdx.x; e < N1 * 8; e += MF_THREADS) tile[e] = Y2[(q << (l1 + 3)) + e];
+    for (int e = threadIdx.x; e < (N1 << lcb); e += MF_THREADS) tile[e] = Y2[(q << (l1 + lcb)) + e];
     __syncthreads();
-    lds_fft(tile, l1, 3, 3, 0, +1, tw, log2M());
+    lds_fft(tile, l1, lcb, lcb, 0, +1, tw, log2M());
     double* td = reinterpret_cast<double*>(tile);
     for (int base = 0; base < units; base += MF_THREADS * U) {
       if (base > 0) {
@@ -426,10 +437,10 @@ struct OpPdct {
     for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
       const int s = u2 >= N2;
       const int u = u2 - s * N2;
-      const int q = u >> 3, c = u & 7;
-      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+      const int q = u >> lcb, c = u & ((1 << lcb) - 1);
+      const int j2 = col_j2(q, c);
       const int k1 = s ? k1b : k1a;
-      const int gi = (((q << l1) + k1) << 3) + c;
+      const int gi = (((q << l1) + k1) << lcb) + c;
       cplx v = Y1[gi];
       if (mode == PB_HAPPLY) {
         if (!first) {
@@ -467,12 +478,12 @@ struct OpPdct {
     for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
       const int s = u2 >= N2;
       const int u = u2 - s * N2;
-      const int q = u >> 3, c = u & 7;
-      const int j2 = c < 4 ? 4 * q + c : N2 - 1 - 4 * q - (c - 4);
+      const int q = u >> lcb, c = u & ((1 << lcb) - 1);
+      const int j2 = col_j2(q, c);
       const int k1 = s ? k1b : k1a;
       cplx v = tile[s * N2 + j2];
       v = cmul(v, tw.get((j2 * k1) << 3, +1));
-      Y2[(((q << l1) + k1) << 3) + c] = v;
+      Y2[(((q << l1) + k1) << lcb) + c] = v;
     }
     __syncthreads();
   }
