@@ -71,6 +71,42 @@ def counter_traffic(workload: str):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def _counter_rows(path: str):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def write_traffic(workload: str, fetch_csv: str, write_csv: str, calib_mb: int):
+    """Turns two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; each with
+    --copy-calib-mb) into profiles/traffic.json: per-launch bytes of the
+    solve kernel, each counter scaled by what it reads for the device copy of
+    calib_mb MiB (calib_mb MiB fetched and written)."""
+    rec = {"src_hash": kernel_src_hash()}
+    for what, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _counter_rows(path)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        solves = [r for r in rows if "k_mfipm" in r["Kernel_Name"]]
+        if not copies or not solves:
+            raise SystemExit(f"{path}: no calibration copy or no solve kernel in the counter file")
+        scale = (calib_mb << 20) / (max(copies) * 1024.0)
+        per_launch = float(np.mean([float(r["Counter_Value"]) for r in solves])) * 1024.0 * scale
+        rec[f"{what}_scale"] = scale
+        rec[f"{what}_bytes_per_launch"] = per_launch
+        rec[f"{what}_kib_raw_per_launch"] = float(np.mean([float(r["Counter_Value"]) for r in solves]))
+        rec["kernel"] = solves[0]["Kernel_Name"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[workload] = rec
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(json.dumps({workload: rec}))
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "pdct":
@@ -316,7 +352,14 @@ def main():
     ap.add_argument("--tune-out", default=None, help="tuning table to write (default: the shipped one)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="write profiles/traffic.json for --workload from two rocprofv3 counter files "
+                         "(needs --copy-calib-mb as used in those runs); runs nothing on the GPU")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(make_workload(args.workload)[2], args.traffic_from[0], args.traffic_from[1],
+                      args.copy_calib_mb)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
               "(instances shard across GPUs without communication; see the design notes)",
