@@ -45,8 +45,8 @@ struct InstDesc {
 // per-team workspace (device pointers)
 struct TeamWS {
   double2 *X, *R, *P, *TI, *DZ, *DS, *Zs, *Ss;
-  double *D, *Yv, *PT, *Dp0, *Dp1;
-  cplx *Y1, *Y1p, *Y2;
+  double *D, *Yv, *PT, *Dp0, *Dp1, *Dx0, *Dx1, *Dd;
+  cplx *Y1, *Y1p, *Y2, *Yx, *Yd;
   unsigned char* mask;
   double *bt, *XS;
   double *partA, *partB, *partC, *partS;
@@ -56,7 +56,8 @@ struct TeamWS {
 };
 
 struct TeamLayout {  // byte offsets inside one team region
-  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Dp0, Dp1, Y1, Y1p, Y2, mask, bt, XS, partA, partB, partC, partS;
+  long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Dp0, Dp1, Dx0, Dx1, Dd, Y1, Y1p, Y2, Yx, Yd, mask, bt, XS, partA, partB,
+      partC, partS;
   int pt_chunks;  // dense fused path: capacity of PT in chunks
   long stride;
 };
@@ -106,6 +107,11 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   w.PT = (double*)(base + a.lay.PT);
   w.Dp0 = (double*)(base + a.lay.Dp0);
   w.Dp1 = (double*)(base + a.lay.Dp1);
+  w.Dx0 = (double*)(base + a.lay.Dx0);
+  w.Dx1 = (double*)(base + a.lay.Dx1);
+  w.Dd = (double*)(base + a.lay.Dd);
+  w.Yx = (cplx*)(base + a.lay.Yx);
+  w.Yd = (cplx*)(base + a.lay.Yd);
   w.Y1p = (cplx*)(base + a.lay.Y1p);
   w.Y1 = (cplx*)(base + a.lay.Y1);
   w.Y2 = (cplx*)(base + a.lay.Y2);
@@ -185,7 +191,9 @@ struct FPcgC2 {
 
 // Residual pass A: bring (z, s) up to date (initial point, pending step) or
 // form the trial point of the corrector; d = x = u - v.
-// acc0 += 1^T z, acc1 += z^T s.
+// acc0 += 1^T z, acc1 += z^T s.  As an elementwise functor (elem) it serves
+// the residual pass B of the later iterations, whose operator input is formed
+// by linearity instead.
 enum { RA_INIT = 0, RA_STEP = 1, RA_TRIAL = 2, RA_NONE = 3 };
 struct FResA {
   static constexpr int K = 2;
@@ -230,6 +238,7 @@ struct FResA {
     acc[1] += z.x * s.x + z.y * s.y;
     return z.x - z.y;
   }
+  __device__ void elem(long i, const In& in) { (void)gather(i, in); }
 };
 
 // Residual pass C: with g = A^T (A x - b) build the Newton right-hand side
@@ -295,7 +304,9 @@ struct FResC {
 // Step pass (elementwise).  Predictor: ds = f_s / z - Theta^{-1} dz
 // (eq. (redNewtonB)), store DZ, DS.  Corrector: the same at the trial point
 // with sigma3, added to the stored predictor direction.  acc0 = min ratio
-// over dz < 0 of -z/dz, acc1 likewise for s.
+// over dz < 0 of -z/dz, acc1 likewise for s.  Run as a gather pass, it hands
+// dz_u - dz_v to the operator's first stage, whose result (the transform of
+// the x-direction) the next residual combines by linearity.
 struct FStep {
   static constexpr int K = 2;
   struct In {
@@ -322,7 +333,7 @@ struct FStep {
       in.ds = DS[i];
     }
   }
-  __device__ void elem(long i, const In& in) {
+  __device__ double gather(long i, const In& in) {
     double2 dz, ds;
     if (!corr) {
       dz = in.x;
@@ -342,6 +353,7 @@ struct FStep {
     if (dz.y < 0) acc[0] = fmin(acc[0], -in.z.y / dz.y);
     if (ds.x < 0) acc[1] = fmin(acc[1], -in.s.x / ds.x);
     if (ds.y < 0) acc[1] = fmin(acc[1], -in.s.y / ds.y);
+    return dz.x - dz.y;
   }
 };
 
@@ -504,6 +516,18 @@ __device__ __forceinline__ void op_direction(OpDense& op, const TeamWS& w, int i
 }
 __device__ __forceinline__ void op_direction(OpPdct&, const TeamWS&, int) {}
 
+// The operator's first stage (pass A) writes the transform of the step
+// direction instead of the operator input (on = 1), or back (on = 0).
+__device__ __forceinline__ void op_step_target(OpDense& op, const TeamWS& w, int on) { op.D = on ? w.Dd : w.D; }
+__device__ __forceinline__ void op_step_target(OpPdct& op, const TeamWS& w, int on) { op.Y1 = on ? w.Yd : w.Y1; }
+// After a residual pass B that kept x: dense swaps its current / next x.
+__device__ __forceinline__ void op_x_advance(OpDense& op) {
+  double* t = op.Dxc;
+  op.Dxc = op.Dxn;
+  op.Dxn = t;
+}
+__device__ __forceinline__ void op_x_advance(OpPdct&) {}
+
 // elementwise pass over [0, n), items of 1024 indices
 template <class F>
 __device__ __forceinline__ void run_E(Ctx& cx, long n, F& f, const int (&kinds)[F::K], double* part) {
@@ -528,6 +552,51 @@ __device__ __forceinline__ void run_E(Ctx& cx, long n, F& f, const int (&kinds)[
 }
 __device__ __forceinline__ int nE(long n) { return (int)((n + 1023) / 1024); }
 
+// Elementwise work that shares a pass with nb operator items: it goes to the
+// workgroups without an operator item when there are any (items of 2^lchunk
+// indices, at most one per such workgroup), else to all in items of 1024.
+__device__ __forceinline__ void span_E(const Ctx& cx, long n, int nb, int& r0, int& nr, int& lchunk) {
+  if (nb < cx.t.size) {
+    r0 = nb;
+    nr = cx.t.size - nb;
+    lchunk = 10;
+    while ((((n + (1L << lchunk) - 1) >> lchunk)) > nr) ++lchunk;
+  } else {
+    r0 = 0;
+    nr = cx.t.size;
+    lchunk = 10;
+  }
+}
+
+// elementwise pass over [0, n) in items of 2^lchunk (>= 1024) indices, item j
+// taken by team rank r0 + (j mod nr)
+template <class F>
+__device__ __forceinline__ void run_E_span(Ctx& cx, long n, F& f, const int (&kinds)[F::K], double* part, int r0,
+                                           int nr, int lchunk) {
+  const int ni = (int)((n + (1L << lchunk) - 1) >> lchunk);
+  const int me = cx.t.rank - r0;
+  if (me < 0 || me >= nr) return;
+  for (int it = me; it < ni; it += nr) {
+    f.reset();
+    const long end = ((long)(it + 1) << lchunk) < n ? ((long)(it + 1) << lchunk) : n;
+    for (long base = (long)it << lchunk; base < end; base += 1024) {
+      constexpr int U = 1024 / MF_THREADS;
+      typename F::In in[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const long i = base + threadIdx.x + k * MF_THREADS;
+        if (i < end) f.load(i, in[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const long i = base + threadIdx.x + k * MF_THREADS;
+        if (i < end) f.elem(i, in[k]);
+      }
+    }
+    finish_item(cx, f, kinds, part, it);
+  }
+}
+
 // ------------------------------------------------------------------------
 // Operator construction and set-up
 // ------------------------------------------------------------------------
@@ -543,8 +612,12 @@ __device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstD
   op.PT = w.PT;
   op.Dp_prev = w.Dp1;
   op.Dp_cur = w.Dp0;
+  op.Dxc = w.Dx0;
+  op.Dxn = w.Dx1;
+  op.Dd = w.Dd;
   op.RB = a.tile_param > 0 ? (a.tile_param > DN_RBMAX ? DN_RBMAX : a.tile_param) : 8;
   op.lds = (double*)lds;
+  op.dsh = (double2*)(lds + (MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double));
   op.fused = (d.n <= DN_FUSED_MAXN) && ((d.n & 1) == 0) && a.lay.pt_chunks > 0;
   // fused: chunks of whole row blocks, at most one per workgroup of the team
   const long blocks = (d.m + DN_FB - 1) / DN_FB;
@@ -584,6 +657,8 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.b = a.b ? a.b + d.m_off : nullptr;
   op.Y1 = w.Y1;
   op.Y1p = w.Y1p;
+  op.Yx = w.Yx;
+  op.Yd = w.Yd;
   op.Y2 = w.Y2;
   op.mask = w.mask;
   op.bt = w.bt;
@@ -750,25 +825,42 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
   fa.s0 = prm.s0;
   fa.mode = mode;
   const int kA[2] = {0, 0};
-  run_A(cx, op, fa, kA, w.partA);
-  if (team_barrier(cx.t)) {
-    o.status = ST_ABORTED;
-    return o;
+  const int kb[2] = {0, 0};
+  double pA[2], pB[2];
+  if (mode == RA_INIT) {
+    // set z, s and gather x through pass A; pass B keeps the transform of x
+    run_A(cx, op, fa, kA, w.partA);
+    if (team_barrier(cx.t)) {
+      o.status = ST_ABORTED;
+      return o;
+    }
+    reduce_items<2>(kA, w.partA, op.nA(), pA, cx.red);
+    run_B<OP>(cx, op, 1, w.partB, nullptr);
+    if (team_barrier(cx.t)) {
+      o.status = ST_ABORTED;
+      return o;
+    }
+    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
+    op_x_advance(op);
+  } else {
+    // The step pass left the transform of the step direction; the operator's
+    // input at the new (or trial) point is x + aP dx by linearity, formed in
+    // pass B, whose idle workgroups meanwhile apply the step to (z, s) (or
+    // form the trial point) and sum 1^T z and z^T s.
+    run_B<OP>(cx, op, mode == RA_STEP ? 3 : 4, w.partB, nullptr, aP, 0);
+    int r0, nr, lchunk;
+    span_E(cx, op.n, op.nB(), r0, nr, lchunk);
+    run_E_span(cx, op.n, fa, kA, w.partS, r0, nr, lchunk);
+    if (team_barrier(cx.t)) {
+      o.status = ST_ABORTED;
+      return o;
+    }
+    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
+    reduce_items<2>(kA, w.partS, (int)((op.n + (1L << lchunk) - 1) >> lchunk), pA, cx.red);
+    if (mode == RA_STEP) op_x_advance(op);
   }
-  double pA[2];
-  reduce_items<2>(kA, w.partA, op.nA(), pA, cx.red);
   o.sumz = pA[0];
   o.zs = pA[1];
-  run_B<OP>(cx, op, 1, w.partB, nullptr);
-  if (team_barrier(cx.t)) {
-    o.status = ST_ABORTED;
-    return o;
-  }
-  double pB[2];
-  {
-    const int kb[2] = {0, 0};
-    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
-  }
   o.rb2 = pB[0];
   o.brb = pB[1];
   FResC fc;
@@ -874,13 +966,15 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
       fs.mu = mu;
       fs.corr = 0;
       fs.aPp = fs.aDp = 0.0;
-      run_E(cx, n, fs, kS, w.partS);
+      op_step_target(op, w, 1);
+      run_A(cx, op, fs, kS, w.partA);
+      op_step_target(op, w, 0);
       if (team_barrier(cx.t)) {
         status = ST_ABORTED;
         break;
       }
       double rs[2];
-      reduce_items<2>(kS, w.partS, nE(n), rs, cx.red);
+      reduce_items<2>(kS, w.partA, op.nA(), rs, cx.red);
       aP = fmin(1.0, prm.eta * rs[0]);
       aD = fmin(1.0, prm.eta * rs[1]);
       if (aP <= prm.alpha_tilde || aD <= prm.alpha_tilde) {
@@ -903,12 +997,14 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
         fs.corr = 1;
         fs.aPp = aP;
         fs.aDp = aD;
-        run_E(cx, n, fs, kS, w.partS);
+        op_step_target(op, w, 1);
+        run_A(cx, op, fs, kS, w.partA);
+        op_step_target(op, w, 0);
         if (team_barrier(cx.t)) {
           status = ST_ABORTED;
           break;
         }
-        reduce_items<2>(kS, w.partS, nE(n), rs, cx.red);
+        reduce_items<2>(kS, w.partA, op.nA(), rs, cx.red);
         aP = fmin(1.0, prm.eta * rs[0]);
         aD = fmin(1.0, prm.eta * rs[1]);
         ++ncorr;

@@ -127,12 +127,17 @@ TeamLayout team_layout(int op_kind, long long n, long long m, int pt_chunks) {
     take(L.PT, (size_t)L.pt_chunks * (size_t)n * sizeof(double));
     take(L.Dp0, (size_t)n * sizeof(double));  // previous/current direction,
     take(L.Dp1, (size_t)n * sizeof(double));  // alternating per PCG iteration
-    L.Y1 = L.Y1p = L.Y2 = L.mask = L.bt = L.XS = 0;
+    take(L.Dx0, (size_t)n * sizeof(double));  // current / next x = u - v
+    take(L.Dx1, (size_t)n * sizeof(double));
+    take(L.Dd, (size_t)n * sizeof(double));   // step direction dz_u - dz_v
+    L.Y1 = L.Y1p = L.Y2 = L.Yx = L.Yd = L.mask = L.bt = L.XS = 0;
   } else {
-    L.D = L.Yv = L.PT = L.Dp0 = L.Dp1 = 0;
+    L.D = L.Yv = L.PT = L.Dp0 = L.Dp1 = L.Dx0 = L.Dx1 = L.Dd = 0;
     L.pt_chunks = 0;
     take(L.Y1, (size_t)n * sizeof(double));  // n/2 complex
     take(L.Y1p, (size_t)n * sizeof(double));  // transform of the direction
+    take(L.Yx, (size_t)n * sizeof(double));   // transform of x = u - v
+    take(L.Yd, (size_t)n * sizeof(double));   // transform of the step direction
     take(L.Y2, (size_t)n * sizeof(double));
     take(L.mask, (size_t)n);
     take(L.bt, (size_t)n * sizeof(double));
@@ -205,7 +210,8 @@ const void* pick_kernel(int op_kind, int bwd) {
 // (lo_bits / hi entries of the call, or the largest supported, n = 2^20).
 constexpr int kPdctMaxLog2N = 20;
 size_t dyn_lds(int op_kind, int lo_bits = -1, long long hi_count = 0) {
-  if (op_kind == MFIPM_OP_DENSE) return (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double);
+  if (op_kind == MFIPM_OP_DENSE)
+    return (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double) + DN_FUSED_MAXN * sizeof(double2);
   if (lo_bits < 0) {
     const int lm = kPdctMaxLog2N + 2;
     lo_bits = (lm + 1) / 2;

@@ -28,7 +28,11 @@
 #define DN_FUSED_MAXN (DN_CPT * MF_THREADS)
 #define DN_FB 2                  // rows per fused block
 
-enum { DB_HAPPLY = 0, DB_RESID = 1, DB_OUT = 2 };
+// pass-B modes.  RESID reads D (x gathered by a pass A) and keeps it in Dxn
+// (chunk 0); RESID_STEP forms Dxc + a Dd by linearity (Dd: the step
+// direction's dz_u - dz_v) and keeps it in Dxn; RESID_TRIAL forms it without
+// keeping it.  The caller swaps Dxc and Dxn after a kept residual.
+enum { DB_HAPPLY = 0, DB_RESID = 1, DB_OUT = 2, DB_RESID_STEP = 3, DB_RESID_TRIAL = 4 };
 
 struct OpDense {
   long n;
@@ -40,12 +44,16 @@ struct OpDense {
   double* Yv;
   double* Dp_prev;  // PCG: d of the previous search direction (read)
   double* Dp_cur;   // PCG: d of the current search direction (written by item 0)
+  double* Dxc;      // current x = u - v (read)
+  double* Dxn;      // next x (written by item 0)
+  double* Dd;       // step direction dz_u - dz_v
   double* PT;  // fused: partial t, nchunk x n
   int RB;
   int fused;
   int nchunk;      // fused: chunks (pass-B items)
   int chunk_rows;  // fused: rows per chunk (multiple of DN_FB)
   double* lds;     // reduction scratch: >= MF_WAVES * DN_RBMAX + DN_RG * DN_CB doubles
+  double2* dsh;    // LDS: the workgroup's d, then its partial t, on the fused path (DN_FUSED_MAXN / 2 pairs each)
 
   __device__ int nA() const { return (int)((n + DN_TA - 1) / DN_TA); }
   __device__ int nB() const { return fused ? nchunk : (int)((m + RB - 1) / RB); }
@@ -71,33 +79,46 @@ struct OpDense {
 
   // ---- fused pass B over one chunk of rows ----
   // Thread t owns the column pairs p = t + MF_THREADS k, k < CPT/2 (columns 2p, 2p+1,
-  // loaded as one 16-byte double2).  acc valid in thread 0: acc[0] += sum y^2,
+  // loaded as one 16-byte double2).  Its values of d and its partial t live in
+  // registers for CPT <= 8 and in LDS for wider rows (each thread reads back
+  // only what it wrote, so no barrier), which keeps the registers for the
+  // streamed rows.  acc valid in thread 0: acc[0] += sum y^2,
   // acc[1] += sum b*y (RESID).  Mode OUT writes y to `out` and skips the
   // transposed product.
   template <int CPT>
-  __device__ __forceinline__ void passB_fused(int item, int mode, double (&acc)[2], double* out, double beta,
+  __device__ __forceinline__ void passB_fused(int item, int mode_in, double (&acc)[2], double* out, double beta,
                                               int first) {
+    const int mode = mode_in >= DB_RESID_STEP ? DB_RESID : mode_in;
     constexpr int KP = CPT / 2;
     const long r_begin = (long)item * chunk_rows;
     const long r_end = (r_begin + chunk_rows) < m ? (r_begin + chunk_rows) : m;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long npair = n >> 1;  // n is even on this path
-    double2 dv[KP], tacc[KP];
-    const double2* D2 = reinterpret_cast<const double2*>(D);
-    const double2* P2 = reinterpret_cast<const double2*>(Dp_prev);
-    double2* C2 = reinterpret_cast<double2*>(Dp_cur);
+    constexpr bool INLDS = CPT > 8;
+    double2 dreg[INLDS ? 1 : KP], treg[INLDS ? 1 : KP];
+    double2* tsh = dsh + DN_FUSED_MAXN / 2;
+    auto dv_at = [&](int k) -> double2 { return INLDS ? dsh[tid + k * MF_THREADS] : dreg[INLDS ? 0 : k]; };
+    auto t_at = [&](int k) -> double2& { return INLDS ? tsh[tid + k * MF_THREADS] : treg[INLDS ? 0 : k]; };
+    const bool lin = mode_in >= DB_RESID_STEP;
+    const double2* D2 = reinterpret_cast<const double2*>(lin ? Dxc : D);
+    const double2* P2 = reinterpret_cast<const double2*>(lin ? Dd : Dp_prev);
+    double2* C2 = reinterpret_cast<double2*>(mode == DB_HAPPLY ? Dp_cur : Dxn);
+    const bool comb = mode == DB_HAPPLY ? !first : lin;
+    const bool keep = mode == DB_HAPPLY || mode_in == DB_RESID || mode_in == DB_RESID_STEP;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const long p = tid + (long)k * MF_THREADS;
-      dv[k] = p < npair ? D2[p] : make_double2(0.0, 0.0);
-      if (mode == DB_HAPPLY && p < npair) {
-        if (!first) {
+      double2 dv = p < npair ? D2[p] : make_double2(0.0, 0.0);
+      if (p < npair) {
+        if (comb) {
           const double2 w = P2[p];
-          dv[k] = make_double2(dv[k].x + beta * w.x, dv[k].y + beta * w.y);
+          dv = make_double2(dv.x + beta * w.x, dv.y + beta * w.y);
         }
-        if (item == 0) C2[p] = dv[k];
+        if (keep && item == 0) C2[p] = dv;
       }
-      tacc[k] = make_double2(0.0, 0.0);
+      if (INLDS) dsh[tid + k * MF_THREADS] = dv;
+      else dreg[INLDS ? 0 : k] = dv;
+      t_at(k) = make_double2(0.0, 0.0);
     }
     double* red = lds;  // [2 parities][MF_WAVES][DN_FB]
     int parity = 0;
@@ -115,7 +136,10 @@ struct OpDense {
           a[r][k] = (rv && p < npair) ? row[p] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int k = 0; k < KP; ++k) sr += a[r][k].x * dv[k].x + a[r][k].y * dv[k].y;
+        for (int k = 0; k < KP; ++k) {
+          const double2 dv = dv_at(k);
+          sr += a[r][k].x * dv.x + a[r][k].y * dv.y;
+        }
         s[r] = sr;
       }
 #pragma unroll
@@ -144,13 +168,13 @@ struct OpDense {
       if (mode != DB_OUT) {
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-          double2 t = tacc[k];
+          double2 t = t_at(k);
 #pragma unroll
           for (int r = 0; r < DN_FB; ++r) {
             t.x += a[r][k].x * y[r];
             t.y += a[r][k].y * y[r];
           }
-          tacc[k] = t;
+          t_at(k) = t;
         }
       }
     }
@@ -159,7 +183,7 @@ struct OpDense {
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
         const long p = tid + (long)k * MF_THREADS;
-        if (p < npair) pt[p] = tacc[k];
+        if (p < npair) pt[p] = t_at(k);
       }
     }
     __syncthreads();
@@ -201,19 +225,24 @@ struct OpDense {
   // y_r = A[r,:] . D for the rows of the block; mode RESID subtracts b,
   // mode OUT writes y to `out` instead of Yv.  acc[0] += sum y^2,
   // acc[1] += sum b*y (RESID).  Results valid in thread 0.
-  __device__ __forceinline__ void passB_rows(int item, int mode, double (&acc)[2], double* out, double beta,
+  __device__ __forceinline__ void passB_rows(int item, int mode_in, double (&acc)[2], double* out, double beta,
                                              int first) {
+    const int mode = mode_in >= DB_RESID_STEP ? DB_RESID : mode_in;
+    const bool lin = mode_in >= DB_RESID_STEP;
+    const double* Din = lin ? Dxc : D;
+    const double* Pin = lin ? Dd : Dp_prev;
+    double* Cout = mode == DB_HAPPLY ? Dp_cur : Dxn;
+    const bool comb = mode == DB_HAPPLY ? !first : lin;
+    const bool keep = mode == DB_HAPPLY || mode_in == DB_RESID || mode_in == DB_RESID_STEP;
     const long r0 = (long)item * RB;
     const int nr = (int)((m - r0) < RB ? (m - r0) : RB);
     double s[DN_RBMAX];
 #pragma unroll
     for (int r = 0; r < DN_RBMAX; ++r) s[r] = 0.0;
     for (long c = threadIdx.x; c < n; c += MF_THREADS) {
-      double dv = D[c];
-      if (mode == DB_HAPPLY) {
-        if (!first) dv += beta * Dp_prev[c];
-        if (item == 0) Dp_cur[c] = dv;
-      }
+      double dv = Din[c];
+      if (comb) dv += beta * Pin[c];
+      if (keep && item == 0) Cout[c] = dv;
 #pragma unroll
       for (int r = 0; r < DN_RBMAX; ++r)
         if (r < nr) s[r] += A[(r0 + r) * lda + c] * dv;

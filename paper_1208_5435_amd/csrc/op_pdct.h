@@ -173,8 +173,11 @@ __device__ __forceinline__ void lds_fft(cplx* buf, int lL, int lcount, int lis, 
   }
 }
 
-// pass-B modes
-enum { PB_HAPPLY = 0, PB_RESID = 1, PB_FWDOUT = 2 };
+// pass-B modes.  RESID reads Y1 (x gathered by a pass A) and keeps it as the
+// transform of the current x in Yx; RESID_STEP forms Yx + a Yd by linearity
+// (Yd: the transform of the step direction) and keeps it; RESID_TRIAL forms
+// it without keeping it.
+enum { PB_HAPPLY = 0, PB_RESID = 1, PB_FWDOUT = 2, PB_RESID_STEP = 3, PB_RESID_TRIAL = 4 };
 
 struct OpPdct {
   long n;
@@ -186,6 +189,8 @@ struct OpPdct {
   cplx* Y1;
   cplx* Y1p;  // column-FFT data of the current search direction (PCG)
   cplx* Y2;
+  cplx* Yx;   // column-FFT data of the current x = u - v
+  cplx* Yd;   // column-FFT data of the step direction dz_u - dz_v
   unsigned char* mask;  // spectral layout, n bytes
   double* bt;           // spectral layout, n doubles
   double* XS;           // spectral layout, n doubles (forward output)
@@ -422,7 +427,9 @@ struct OpPdct {
 
   // ---- pass B: two rows of Y1 -> row FFT -> spectral -> row IFFT -> Y2 ----
   // Mode HAPPLY combines the rows first: Y1p <- Y1 (+ beta Y1p unless first).
-  __device__ __forceinline__ void passB(int r, int mode, double (&acc)[2], double beta, int first) {
+  // The residual modes take the rows as described at the mode list (beta = a).
+  __device__ __forceinline__ void passB(int r, int mode_in, double (&acc)[2], double beta, int first) {
+    const int mode = mode_in >= PB_RESID_STEP ? PB_RESID : mode_in;  // spectral treatment
     const int k1a = r == 0 ? 0 : r;
     const int k1b = r == 0 ? (N1 >> 1) : N1 - r;
     cur_k1a = k1a;
@@ -441,13 +448,22 @@ struct OpPdct {
       const int j2 = col_j2(q, c);
       const int k1 = s ? k1b : k1a;
       const int gi = (((q << l1) + k1) << lcb) + c;
-      cplx v = Y1[gi];
-      if (mode == PB_HAPPLY) {
-        if (!first) {
-          const cplx w = Y1p[gi];
-          v = mkc(v.x + beta * w.x, v.y + beta * w.y);
+      cplx v;
+      if (mode_in >= PB_RESID_STEP) {
+        const cplx a = Yx[gi], d = Yd[gi];
+        v = mkc(a.x + beta * d.x, a.y + beta * d.y);
+        if (mode_in == PB_RESID_STEP) Yx[gi] = v;
+      } else {
+        v = Y1[gi];
+        if (mode == PB_HAPPLY) {
+          if (!first) {
+            const cplx w = Y1p[gi];
+            v = mkc(v.x + beta * w.x, v.y + beta * w.y);
+          }
+          Y1p[gi] = v;
+        } else if (mode == PB_RESID) {
+          Yx[gi] = v;
         }
-        Y1p[gi] = v;
       }
       tile[s * N2 + j2] = v;
     }
