@@ -361,7 +361,7 @@ def main():
                       args.copy_calib_mb)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(instances shard across GPUs without communication; see the design notes)",
               file=sys.stderr)
         raise SystemExit(2)
