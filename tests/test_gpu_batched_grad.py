@@ -225,3 +225,30 @@ def test_autograd_batched_shared_dct(solver):
             assert U.rel(gb[j].cpu().numpy(), gb_cf) <= 1e-5, j
             assert abs(float(gt[j]) - gt_cf) <= 1e-5 * abs(gt_cf), j
     assert well_posed >= 2
+
+
+@pytest.mark.parametrize("team,total", [(3, 0), (5, 40), (7, 21), (12, 0)])
+def test_batched_odd_team_sizes(solver, team, total):
+    """Teams whose workgroups spread unevenly over the XCDs (the team barrier
+    groups a team's workgroups by the XCD they run on): every instance of an
+    uneven batch converges and agrees with its single solve to the parity bar,
+    whatever the team size and number of teams (the item shape, and so the
+    last bits, may differ from the single solve's)."""
+    insts = [W.dct_instance(n, n // 4, max(2, n // 100), seed=900 + i)
+             for i, n in enumerate([1024, 4096, 2048, 8192, 512, 4096, 1024, 2048, 16384])]
+    n_off = _offsets([i.n for i in insts])
+    m_off = _offsets([i.m for i in insts])
+    rows = np.concatenate([i.rows for i in insts])
+    b = np.concatenate([i.b for i in insts])
+    say(f"odd teams: team={team} workgroups={total}")
+    solver.set_launch(total, team, 0)
+    try:
+        res = solver.solve_batched(b, [i.tau for i in insts], n_off, m_off, rows=rows)
+    finally:
+        solver.set_launch(0, 0, 0)
+    xb = res.x.cpu().numpy()
+    for j, inst in enumerate(insts):
+        r1 = solver.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n)
+        x1 = r1.x.cpu().numpy()
+        assert res.infos[j]["status"] == 0, (j, res.infos[j])
+        assert np.linalg.norm(x1 - xb[n_off[j]:n_off[j + 1]]) <= 1e-6 * (1.0 + np.linalg.norm(x1)), j
