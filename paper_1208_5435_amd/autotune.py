@@ -45,10 +45,25 @@ def _load(path):
         return {}
 
 
+_memo = {}  # path -> (mtime, table): tables are re-read only when the file changes
+
+
+def _table(path):
+    try:
+        mtime = os.stat(path).st_mtime_ns
+    except OSError:
+        return {}
+    hit = _memo.get(path)
+    if hit is None or hit[0] != mtime:
+        hit = (mtime, _load(path))
+        _memo[path] = hit
+    return hit[1]
+
+
 def lookup(key: str):
     """Tuned (workgroups, team_size, tile) for `key`, or None."""
     for path in (user_cache_path(), SHIPPED):
-        rec = _load(path).get(key)
+        rec = _table(path).get(key)
         if rec:
             return tuple(rec["shape"])
     return None
