@@ -72,6 +72,9 @@ struct mfipm_handle {
   size_t scratch_lane[2][2];  // [op][bwd] private bytes per lane
   // twiddle tables (device, owned by the handle), one per table resolution
   cplx* tw[32];
+  // pinned host staging for the per-call uploads and read-backs
+  char* pinned;
+  size_t pinned_bytes;
 };
 
 // Upper bound on private (scratch) memory of one dispatch: all workgroups of a
@@ -356,9 +359,21 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   if (ws_bytes < gl.total) return MFIPM_ERR_WORKSPACE_TOO_SMALL;
 
   char* base = (char*)ws;
-  // host-side tables: descriptors followed by the launch order (one upload)
-  std::vector<char> desc((size_t)P.batch * (sizeof(InstDesc) + sizeof(int)));
-  InstDesc* inst = reinterpret_cast<InstDesc*>(desc.data());
+  // Pinned staging (the previous call has synchronised): descriptors and the
+  // launch order go up in one copy; reports and the abort flag come back into
+  // the same buffer.
+  const size_t desc_bytes = (size_t)P.batch * (sizeof(InstDesc) + sizeof(int));
+  const size_t back_bytes = align_up((size_t)P.batch * sizeof(DevInfo)) + 256;
+  const size_t need = std::max(desc_bytes, back_bytes);
+  if (h->pinned_bytes < need) {
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+    if (hipHostMalloc((void**)&h->pinned, need, hipHostMallocDefault) != hipSuccess) return MFIPM_ERR_HIP;
+    h->pinned_bytes = need;
+  }
+  char* desc = h->pinned;
+  InstDesc* inst = reinterpret_cast<InstDesc*>(desc);
   std::vector<int> order(P.batch);
   for (int i = 0; i < P.batch; ++i) {
     inst[i].n = P.n_off[i + 1] - P.n_off[i];
@@ -375,8 +390,8 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     return cu > cv;
   });
   hipStream_t s = h->stream;
-  std::memcpy(desc.data() + (size_t)P.batch * sizeof(InstDesc), order.data(), sizeof(int) * P.batch);
-  HIP_TRY(hipMemcpyAsync(base + gl.inst, desc.data(), desc.size(), hipMemcpyHostToDevice, s));
+  std::memcpy(desc + (size_t)P.batch * sizeof(InstDesc), order.data(), sizeof(int) * P.batch);
+  HIP_TRY(hipMemcpyAsync(base + gl.inst, desc, desc_bytes, hipMemcpyHostToDevice, s));
   const int logn_max = ilog2_host(P.n_max);
   const cplx* tw = nullptr;
   if (P.op_kind == MFIPM_OP_PDCT) {
@@ -421,10 +436,10 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
                                  (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
     return MFIPM_ERR_HIP;
   HIP_TRY(hipEventRecord(h->ev1, s));
-  std::vector<DevInfo> dinf(P.batch);
-  int ctl[32];
-  HIP_TRY(hipMemcpyAsync(dinf.data(), base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(ctl, base + gl.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+  const DevInfo* dinf = reinterpret_cast<const DevInfo*>(h->pinned);
+  const int* ctl = reinterpret_cast<const int*>(h->pinned + align_up((size_t)P.batch * sizeof(DevInfo)));
+  HIP_TRY(hipMemcpyAsync(h->pinned, base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((void*)ctl, base + gl.ctl, 128, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
@@ -525,6 +540,7 @@ int mfipm_destroy(mfipm_handle* h) {
   (void)hipEventDestroy(h->ev1);
   for (int i = 0; i < 32; ++i)
     if (h->tw[i]) (void)hipFree(h->tw[i]);
+  if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return MFIPM_OK;
 }
