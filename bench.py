@@ -1,25 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark of the MI355X matrix-free IPM solver (one JSON line on stdout).
 
-A step is one complete solve (every IPM iteration with its PCG solves,
-residuals, step lengths, correctors) of one synthetic instance whose inputs
-already sit in device memory.  The default workload is the partial DCT with
-n = 2^16, m = n/4, k = floor(n/100) N(0,1) spikes, noise sigma = 1e-2,
-tau = 1e-2 ||A^T b||_inf.
+A step is one complete call of the hot path on inputs that already sit in
+device memory: every IPM iteration with its PCG solves, residuals, step
+lengths, correctors and the final x = u - v, for every instance of the call.
+The default workload is the uneven dense batch: 256 independent instances in
+one launch, n_i = 64 U{16..128}, m_i = n_i/4, A_i i.i.d. N(0, 1/m_i),
+k_i = floor(n_i/50) N(0,1) spikes, noise sigma = 1e-3,
+tau_i = 1e-2 ||A_i^T b_i||_inf; `value` is solves per second of that batch.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Roofline: algorithmic bytes of one solve launch divided by the kernel's
-duration measured with HIP events on the library's stream (average over
-the timed launches).  Per PCG iteration the method must move the vector
-state (read x, r, p, Theta^{-1}; write x, r, p: 7 * 2n doubles = 112 n
-bytes) and the operator's compulsory traffic (partial DCT: 16 (n + m) bytes;
-dense: the matrix once, 8 m n bytes); per direction computation (IPM
-iteration or corrector) and per residual evaluation it moves ten 2n-vector
-passes (160 n bytes) plus one operator application.
+Workloads: batched_dense (default), pdct_hdr (partial DCT n = 2^20),
+grad (32 signals sharing a partial DCT, n = 2^18, forward + adjoint),
+shared_dense (256 signals sharing one 2048 x 8192 dense A, FP64 MFMA),
+pdct (partial DCT n = 2^16), dense (256 x 1024).
 
-cpu_baseline: the CPU oracle (plain NumPy/SciPy FP64) timed on the host on
-a bounded sample of the same workload.
+Roofline: algorithmic bytes (or flops) of the timed launch divided by its
+duration measured with HIP events on the library's stream (average over the
+timed launches).  Per PCG iteration the method must move the vector state
+(read x, r, p, Theta^{-1}; write x, r, p: 7 x 2n doubles = 112 n bytes) and
+the operator's compulsory traffic (partial DCT: 16 (n + m) bytes; dense: the
+matrix once, 8 m n bytes); per direction computation (IPM iteration or
+corrector) and per residual evaluation it moves ten 2n-vector passes
+(160 n bytes) plus one operator application.  The shared-dense workload is
+bound by FP64 MFMA: 4 m n flops per signal per operator application.
+
+cpu_baseline: the CPU oracle (plain NumPy/SciPy FP64) on a bounded sample of
+the same workload, in worker processes (one host core each) forked from a
+server started before the GPU is touched.
 """
 from __future__ import annotations
 
@@ -35,6 +44,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 METRIC = "l1-LS solves/sec + PCG matvec HBM GB/s (% peak), batched & grad vs plain"
 
 
@@ -43,6 +53,11 @@ def alg_bytes(kind: str, n: int, m: int, info: dict) -> float:
     pcg = info["pcg_iters"] * (112.0 * n + op)
     ipm = (info["ipm_iters"] + info["correctors"] + 1) * (160.0 * n + op)
     return pcg + ipm
+
+
+def adjoint_bytes(kind: str, n: int, m: int, info: dict) -> float:
+    op = 16.0 * (n + m) if kind == "pdct" else 8.0 * m * n
+    return info["pcg_iters"] * (112.0 * n + op) + 2 * (160.0 * n + op)
 
 
 def kernel_src_hash() -> str:
@@ -90,11 +105,12 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, calib_mb: int):
         if not copies or not solves:
             raise SystemExit(f"{path}: no calibration copy or no solve kernel in the counter file")
         scale = (calib_mb << 20) / (max(copies) * 1024.0)
-        per_launch = float(np.mean([float(r["Counter_Value"]) for r in solves])) * 1024.0 * scale
+        vals = [float(r["Counter_Value"]) for r in solves]
         rec[f"{what}_scale"] = scale
-        rec[f"{what}_bytes_per_launch"] = per_launch
-        rec[f"{what}_kib_raw_per_launch"] = float(np.mean([float(r["Counter_Value"]) for r in solves]))
+        rec[f"{what}_bytes_per_launch"] = float(np.mean(vals)) * 1024.0 * scale
+        rec[f"{what}_kib_raw_per_launch"] = float(np.mean(vals))
         rec["kernel"] = solves[0]["Kernel_Name"]
+        rec["launches"] = len(solves)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -107,7 +123,119 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, calib_mb: int):
     print(json.dumps({workload: rec}))
 
 
-def make_workload(name: str):
+def _line(value, unit, args, ms_step, config, roofline, higher=True):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": config, "roofline": roofline}
+
+
+def _hbm_roofline(ab, kernel_ms, kernel, workload):
+    achieved = ab / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
+            "kernel": kernel, "alg_bytes_per_launch": ab}
+
+
+def _timed(run, args, torch):
+    """Warmup, then exactly args.steps timed calls between synchronisations.
+    Returns (wall seconds, kernel ms per call, last result)."""
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    kms = []
+    r = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = run()
+        kms.append(r[1] if isinstance(r, tuple) else r.kernel_ms)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, kms, r
+
+
+# ----------------------------------------------------------------- CPU baselines --
+
+def cpu_baseline_single(kind, inst, budget_s):
+    """Full oracle solves of the same instance on one host core (BLAS limited
+    to one thread; scipy.fft single worker), as many as fit in the budget."""
+    from threadpoolctl import threadpool_limits
+    from oracle import mfipm_ref as R
+    op = R.DenseOperator(inst.A) if kind == "dense" else R.PartialDCTOperator(inst.n, inst.rows)
+    times = []
+    with threadpool_limits(1):
+        t_end = time.perf_counter() + budget_s
+        while True:
+            t0 = time.perf_counter()
+            R.solve(op, inst.b, inst.tau)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() + times[-1] > t_end or len(times) >= 50:
+                break
+    from oracle import pool
+    return {"value": round(len(times) / sum(times), 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host": pool.host_model(),
+            "sample": f"{len(times)} full oracle solves of the same instance ({sum(times):.1f} s on one core)"}
+
+
+def cpu_baseline_batched_dense(sizes, stride):
+    """Every `stride`-th instance of the batch (by size) solved by the oracle
+    in parallel worker processes; the rate is scaled to the whole batch by
+    the sum of m n (the oracle's cost is its matrix passes)."""
+    from oracle import pool
+    order = np.argsort(-sizes, kind="stable")
+    sample = [int(i) for i in order[::stride]]
+    cores = min(pool.host_cores(), len(sample))
+    with pool.executor(cores) as ex:
+        pool.warm(ex, cores)
+        t0 = time.perf_counter()
+        res = list(ex.map(pool.time_batched_dense, sample, [int(sizes[i]) for i in sample]))
+        wall = time.perf_counter() - t0
+    mn = lambda n: (n // 4) * n  # noqa: E731
+    full = float(sum(mn(int(n)) for n in sizes))
+    part = float(sum(mn(int(sizes[i])) for i in sample))
+    est = wall * full / part
+    return {"value": round(len(sizes) / est, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "host": pool.host_model(),
+            "sample": f"{len(sample)} of {len(sizes)} instances (every {stride}th by size, "
+                      f"{part / full:.3f} of the batch's sum m*n) on {cores} worker processes: "
+                      f"{wall:.1f} s wall incl. drawing each instance ({sum(r[0] for r in res):.1f} s of it); "
+                      f"scaled to the batch by sum m*n",
+            "oracle_ipm_iters_sample": [r[2] for r in res]}
+
+
+def cpu_baseline_grad(n, batch, signals):
+    from oracle import pool
+    cores = min(pool.host_cores(), signals)
+    with pool.executor(cores) as ex:
+        pool.warm(ex, cores)
+        t0 = time.perf_counter()
+        res = list(ex.map(pool.time_grad_signal, range(signals), [n] * signals, [batch] * signals))
+        wall = time.perf_counter() - t0
+    return {"value": round(signals / wall, 4), "unit": "signals/s (forward+gradient)", "cores": cores,
+            "kind": "oracle", "host": pool.host_model(),
+            "sample": f"signals 0..{signals - 1} of {batch}: oracle forward solve + oracle adjoint "
+                      f"(PCG to 1e-12) each, {cores} worker processes, {wall:.1f} s wall; "
+                      f"forward {np.mean([r[0] for r in res]):.1f} s and adjoint "
+                      f"{np.mean([r[1] for r in res]):.1f} s per signal"}
+
+
+def cpu_baseline_shared_dense(batch, signals):
+    from oracle import pool
+    cores = min(pool.host_cores(), signals)
+    with pool.executor(cores) as ex:
+        pool.warm(ex, cores)
+        t0 = time.perf_counter()
+        res = list(ex.map(pool.time_shared_dense, range(signals), [batch] * signals))
+        wall = time.perf_counter() - t0
+    return {"value": round(signals / wall, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "host": pool.host_model(),
+            "sample": f"signals 0..{signals - 1} of {batch} (each worker draws A and its signal, then "
+                      f"solves): {cores} worker processes, {wall:.1f} s wall, "
+                      f"{np.mean([r[0] for r in res]):.1f} s per solve"}
+
+
+# ------------------------------------------------------------------ workloads --
+
+def make_single(name: str):
     import workloads as W
     if name == "pdct":
         inst = W.config_pdct()
@@ -121,42 +249,56 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(kind, inst, budget_s: float):
-    """Times the oracle on the host: as many full solves of the same instance
-    as fit in the budget (at least one)."""
-    from oracle import mfipm_ref as R
-    op = R.DenseOperator(inst.A) if kind == "dense" else R.PartialDCTOperator(inst.n, inst.rows)
-    times = []
-    t_end = time.perf_counter() + budget_s
-    while True:
-        t0 = time.perf_counter()
-        R.solve(op, inst.b, inst.tau)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() + times[-1] > t_end or len(times) >= 50:
-            break
+def bench_single(args, torch, Solver):
+    kind, inst, wl = make_single(args.workload)
+    dev = torch.device("cuda", 0)
+    solver = Solver(device=dev)
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = 1
-    cores = 1 if kind == "pdct" else int(blas_threads)
-    return {"value": round(len(times) / sum(times), 4), "unit": "solves/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{len(times)} full oracle solves of the same instance "
-                      f"({sum(times):.1f} s of host time; scipy.fft single worker, numpy elementwise)"}
+        solver.set_launch(args.workgroups, 0, args.tile)
+        b = torch.from_numpy(inst.b).to(dev)
+        if kind == "dense":
+            A = torch.from_numpy(inst.A).to(dev)
+            call = lambda: solver.solve(b, inst.tau, A=A)  # noqa: E731
+        else:
+            rows = torch.from_numpy(inst.rows).to(dev)
+            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n)  # noqa: E731
+        _calibration_copy(args, torch, dev)
+        wall, kms, r = _timed(call, args, torch)
+    finally:
+        solver.close()
+    info = r.infos[0]
+    if info["status"] != 0:
+        print(f"bench.py: solve did not converge: {info}", file=sys.stderr)
+    n, m = inst.n, inst.m
+    kms_mean = float(np.mean(kms))
+    cfg = {"workload": wl, "n": n, "m": m, "tau": inst.tau, "tol": 1e-8, "tolpcg": 1e-2,
+           "ipm_iters": info["ipm_iters"], "pcg_iters": info["pcg_iters"], "correctors": info["correctors"],
+           "nmat": info["nmat"], "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
+           "kernel_ms_min": round(float(np.min(kms)), 4)}
+    kern = "k_mfipm<OpPdct,0>" if kind == "pdct" else "k_mfipm<OpDense,0>"
+    out = _line(round(args.steps / wall, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
+                _hbm_roofline(alg_bytes(kind, n, m, info), kms_mean, kern, wl))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_single(kind, inst, args.cpu_seconds)
+    return out
 
 
-def _pool_map(fn, items, workers=16):
-    from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        return list(ex.map(fn, items))
+def _calibration_copy(args, torch, dev):
+    if args.copy_calib_mb > 0:
+        src = torch.empty(args.copy_calib_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
 
 def batched_dense_inputs(args, torch):
     import workloads as W
+    from concurrent.futures import ThreadPoolExecutor
     sizes = W.batched_dense_sizes(batch=args.batch)
     t0 = time.perf_counter()
-    insts = _pool_map(lambda iv: W.batched_dense_instance(iv[0], int(iv[1])), list(enumerate(sizes)))
+    with ThreadPoolExecutor(16) as ex:
+        insts = list(ex.map(lambda iv: W.batched_dense_instance(iv[0], int(iv[1])), enumerate(sizes)))
     gen_s = time.perf_counter() - t0
     dev = torch.device("cuda", 0)
     n_off = np.concatenate([[0], np.cumsum([i.n for i in insts])]).astype(np.int64)
@@ -167,63 +309,62 @@ def batched_dense_inputs(args, torch):
         A[a_off[j]:a_off[j + 1]].copy_(torch.from_numpy(i.A.reshape(-1)))
     b = torch.from_numpy(np.concatenate([i.b for i in insts])).to(dev)
     taus = np.array([i.tau for i in insts])
-    return insts, gen_s, dev, n_off, m_off, a_off, A, b, taus
+    return sizes, insts, gen_s, dev, n_off, m_off, a_off, A, b, taus
 
 
 def bench_batched_dense(args, torch, Solver):
-    """256 uneven dense instances in one launch vs one launch per instance."""
-    insts, gen_s, dev, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
+    """The uneven dense batch in one launch, against one launch per instance."""
+    sizes, insts, gen_s, dev, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
+    del insts
     solver = Solver(device=dev)
-    solver.set_launch(args.workgroups, args.team, args.tile)
-    run = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
-    for _ in range(args.warmup):
-        run()
-    torch.cuda.synchronize()
-    kms, t0 = [], time.perf_counter()
-    for _ in range(args.steps):
-        r = run()
-        kms.append(r.kernel_ms)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    infos = r.infos
+    try:
+        solver.set_launch(args.workgroups, args.team, args.tile)
+        run = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
+        _calibration_copy(args, torch, dev)
+        wall, kms, r = _timed(run, args, torch)
+        infos = r.infos
+        plain = None
+        if not args.no_plain:
+            solver.set_launch(0, 0, args.tile)
+            t1 = time.perf_counter()
+            plain_iters = 0
+            for j in range(len(sizes)):
+                nj, mj = int(n_off[j + 1] - n_off[j]), int(m_off[j + 1] - m_off[j])
+                rr = solver.solve(b[m_off[j]:m_off[j + 1]], float(taus[j]),
+                                  A=A[a_off[j]:a_off[j + 1]].view(mj, nj))
+                plain_iters += rr.infos[0]["ipm_iters"]
+            torch.cuda.synchronize()
+            plain = (time.perf_counter() - t1, plain_iters)
+    finally:
+        solver.close()
+    B = len(sizes)
     bad = [k for k, i in enumerate(infos) if i["status"] != 0]
     ab = sum(alg_bytes("dense", int(n_off[j + 1] - n_off[j]), int(m_off[j + 1] - m_off[j]), infos[j])
-             for j in range(len(insts)))
-    # plain: one launch per instance, same parameters
-    solver.set_launch(0, 0, args.tile)
-    t1 = time.perf_counter()
-    plain_iters = 0
-    for j, i in enumerate(insts):
-        rr = solver.solve(b[m_off[j]:m_off[j + 1]], i.tau,
-                          A=A[a_off[j]:a_off[j + 1]].view(i.m, i.n))
-        plain_iters += rr.infos[0]["ipm_iters"]
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t1
+             for j in range(B))
     kms_mean = float(np.mean(kms))
-    achieved = ab / (kms_mean * 1e-3) / 1e9
-    return {
-        "metric": METRIC, "value": round(len(insts) * args.steps / wall, 3), "unit": "solves/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"batched_dense_{len(insts)}_n64x16-128_m=n/4",
-                   "batch": len(insts), "sum_mn": int(a_off[-1]), "gen_s": round(gen_s, 1),
-                   "not_converged": bad, "ipm_iters_sum": sum(i["ipm_iters"] for i in infos),
-                   "plain_ipm_iters_sum": plain_iters,
-                   "kernel_ms_mean": round(kms_mean, 3),
-                   "plain_solves_per_s": round(len(insts) / plain_s, 3),
-                   "batched_over_plain": round((len(insts) * args.steps / wall) / (len(insts) / plain_s), 3)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_mfipm<OpDense,0>", "alg_bytes_per_launch": ab},
-    }
+    value = B * args.steps / wall
+    wl = f"batched_dense_{B}_n64x16-128_m=n/4"
+    cfg = {"workload": wl, "batch": B, "sum_mn": int(a_off[-1]), "gen_s": round(gen_s, 1),
+           "not_converged": bad, "ipm_iters_sum": sum(i["ipm_iters"] for i in infos),
+           "pcg_iters_sum": sum(i["pcg_iters"] for i in infos), "kernel_ms_mean": round(kms_mean, 3)}
+    if plain:
+        cfg.update({"plain_solves_per_s": round(B / plain[0], 3), "plain_ipm_iters_sum": plain[1],
+                    "batched_over_plain": round(value / (B / plain[0]), 3)})
+    out = _line(round(value, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
+                _hbm_roofline(ab, kms_mean, "k_mfipm<OpDense,0>", wl))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched_dense(sizes, stride=8)
+    return out
 
 
 def bench_grad(args, torch, Solver):
-    """32 signals sharing a partial DCT: batched forward + adjoint vs per-signal calls."""
+    """32 signals sharing a partial DCT: batched forward + adjoint, against
+    one forward and one adjoint launch per signal."""
     import workloads as W
-    inst = W.config_dct_batch(n=args.grad_n, batch=args.batch if args.batch != 256 else 32)
+    B = args.batch if args.batch != 256 else 32
+    inst = W.config_dct_batch(n=args.grad_n, batch=B)
     dev = torch.device("cuda", 0)
-    B, m = inst.b.shape
+    m = inst.m
     n = inst.n
     n_off = np.arange(B + 1, dtype=np.int64) * n
     m_off = np.arange(B + 1, dtype=np.int64) * m
@@ -231,55 +372,57 @@ def bench_grad(args, torch, Solver):
     b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
     xt = torch.from_numpy(inst.x_true.reshape(-1)).to(dev)
     solver = Solver(device=dev)
-    solver.set_launch(args.workgroups, args.team, args.tile)
+    try:
+        solver.set_launch(args.workgroups, args.team, args.tile)
 
-    def fwd_bwd():
-        r = solver.solve_batched(b, inst.tau, n_off, m_off, rows=rows, shared_op=True)
-        f_ms = r.kernel_ms
-        gb, gt, binf = solver.backward(r.state, r.x - xt, n_off, m_off, rows=rows, shared_op=True)
-        return r, f_ms, solver.last_kernel_ms(), binf
-    for _ in range(args.warmup):
-        fwd_bwd()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fms, bms = [], []
-    for _ in range(args.steps):
-        r, f_ms, b_ms, binf = fwd_bwd()
-        fms.append(f_ms)
-        bms.append(b_ms)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # plain: one forward + one adjoint launch per signal
-    solver.set_launch(0, 0, args.tile)
-    one = np.array([0, n], np.int64)
-    onem = np.array([0, m], np.int64)
-    t1 = time.perf_counter()
-    for j in range(B):
-        rj = solver.solve(b[j * m:(j + 1) * m], float(inst.tau[j]), rows=rows, n=n)
-        solver.backward(rj.state, rj.x - xt[j * n:(j + 1) * n], one, onem, rows=rows)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t1
+        def fwd_bwd():
+            r = solver.solve_batched(b, inst.tau, n_off, m_off, rows=rows, shared_op=True)
+            f_ms = r.kernel_ms
+            gb, gt, binf = solver.backward(r.state, r.x - xt, n_off, m_off, rows=rows, shared_op=True)
+            return (r, f_ms, solver.last_kernel_ms(), binf)
+        _calibration_copy(args, torch, dev)
+        for _ in range(args.warmup):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fms, bms = [], []
+        for _ in range(args.steps):
+            r, f_ms, b_ms, binf = fwd_bwd()
+            fms.append(f_ms)
+            bms.append(b_ms)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        plain_s = None
+        if not args.no_plain:
+            solver.set_launch(0, 0, args.tile)
+            one = np.array([0, n], np.int64)
+            onem = np.array([0, m], np.int64)
+            t1 = time.perf_counter()
+            for j in range(B):
+                rj = solver.solve(b[j * m:(j + 1) * m], float(inst.tau[j]), rows=rows, n=n)
+                solver.backward(rj.state, rj.x - xt[j * n:(j + 1) * n], one, onem, rows=rows)
+            torch.cuda.synchronize()
+            plain_s = time.perf_counter() - t1
+    finally:
+        solver.close()
     infos = r.infos
     ab_f = sum(alg_bytes("pdct", n, m, i) for i in infos)
-    ab_b = sum(binf[j]["pcg_iters"] * (112.0 * n + 16.0 * (n + m)) + 2 * (160.0 * n + 16.0 * (n + m))
-               for j in range(B))
+    ab_b = sum(adjoint_bytes("pdct", n, m, i) for i in binf)
     f_mean, b_mean = float(np.mean(fms)), float(np.mean(bms))
-    achieved = (ab_f + ab_b) / ((f_mean + b_mean) * 1e-3) / 1e9
-    return {
-        "metric": METRIC, "value": round(B * args.steps / wall, 3), "unit": "signals/s (forward+gradient)",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"grad_pdct_batch{B}_n{n}_m{m}", "forward_kernel_ms": round(f_mean, 3),
-                   "backward_kernel_ms": round(b_mean, 3),
-                   "ipm_iters": [i["ipm_iters"] for i in infos],
-                   "adjoint_pcg_iters": [i["pcg_iters"] for i in binf],
-                   "plain_signals_per_s": round(B / plain_s, 3),
-                   "batched_over_plain": round((B * args.steps / wall) / (B / plain_s), 3)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_mfipm<OpPdct,0> + k_mfipm<OpPdct,1>",
-                     "alg_bytes_per_launch": ab_f + ab_b},
-    }
+    value = B * args.steps / wall
+    wl = f"grad_pdct_batch{B}_n{n}_m{m}"
+    cfg = {"workload": wl, "forward_kernel_ms": round(f_mean, 3), "backward_kernel_ms": round(b_mean, 3),
+           "ipm_iters": [i["ipm_iters"] for i in infos], "adjoint_pcg_iters": [i["pcg_iters"] for i in binf],
+           "not_converged": [j for j, i in enumerate(infos) if i["status"] != 0],
+           "adjoint_status": sorted({i["status"] for i in binf})}
+    if plain_s:
+        cfg.update({"plain_signals_per_s": round(B / plain_s, 3),
+                    "batched_over_plain": round(value / (B / plain_s), 3)})
+    roof = _hbm_roofline(ab_f + ab_b, f_mean + b_mean, "k_mfipm<OpPdct,0> + k_mfipm<OpPdct,1>", wl)
+    out = _line(round(value, 3), "signals/s (forward+gradient)", args, 1e3 * wall / args.steps, cfg, roof)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_grad(n, B, min(16, B))
+    return out
 
 
 def tune_workload(args, torch, Solver):
@@ -291,7 +434,7 @@ def tune_workload(args, torch, Solver):
     out = args.tune_out or autotune.SHIPPED
     jobs = []
     if args.workload in ("pdct", "pdct_hdr", "dense"):
-        kind, inst, _ = make_workload(args.workload)
+        kind, inst, _ = make_single(args.workload)
         b = torch.from_numpy(inst.b).to(dev)
         if kind == "dense":
             A = torch.from_numpy(inst.A).to(dev)
@@ -319,7 +462,7 @@ def tune_workload(args, torch, Solver):
         jobs.append((solver.tune_key(1, inst.n, m, B, True), fwd, cands))
         jobs.append((solver.tune_key(1, inst.n, m, B, True, backward=True), bwd, cands))
     elif args.workload == "batched_dense":
-        insts, _, _, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
+        sizes, insts, _, _, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
         call = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
         nmax = int(np.diff(n_off).max())
         mmax = int(np.diff(m_off).max())
@@ -327,24 +470,29 @@ def tune_workload(args, torch, Solver):
                      autotune.candidates(0, nmax, mmax, len(insts), solver.num_cu)))
     else:
         raise SystemExit("--tune supports pdct, pdct_hdr, dense, batched_dense, grad")
-    for key, call, cands in jobs:
-        best, ms, table = autotune.tune(solver, call, key, cands, reps=3, path=out, verbose=True)
-        print(json.dumps({"key": key, "best": best, "kernel_ms": ms,
-                          "table": [[list(s), round(t, 4)] for s, t in table]}), flush=True)
+    try:
+        for key, call, cands in jobs:
+            best, ms, table = autotune.tune(solver, call, key, cands, reps=3, path=out, verbose=True)
+            print(json.dumps({"key": key, "best": best, "kernel_ms": ms,
+                              "table": [[list(s), round(t, 4)] for s, t in table]}), flush=True)
+    finally:
+        solver.close()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pdct",
-                    choices=["pdct", "pdct_hdr", "dense", "batched_dense", "grad"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batched_dense",
+                    choices=["batched_dense", "pdct_hdr", "grad", "pdct", "dense"])
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--grad-n", type=int, default=1 << 18)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the one-launch-per-instance comparison (profiling runs)")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true",
@@ -355,9 +503,10 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="write profiles/traffic.json for --workload from two rocprofv3 counter files "
                          "(needs --copy-calib-mb as used in those runs); runs nothing on the GPU")
+    ap.add_argument("--traffic-key", default=None, help="workload key for --traffic-from")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(make_workload(args.workload)[2], args.traffic_from[0], args.traffic_from[1],
+        write_traffic(args.traffic_key or args.workload, args.traffic_from[0], args.traffic_from[1],
                       args.copy_calib_mb)
         return
     if args.gpus != 1:
@@ -365,82 +514,19 @@ def main():
               "(instances shard across GPUs without communication; see the design notes)",
               file=sys.stderr)
         raise SystemExit(2)
+    if not args.no_cpu_baseline:
+        from oracle import pool
+        pool.start()  # worker server forked before any GPU call
 
     import torch
     from paper_1208_5435_amd import Solver
 
+    torch.cuda.set_device(0)
     if args.tune:
         tune_workload(args, torch, Solver)
         return
-    if args.workload in ("batched_dense", "grad"):
-        fn = bench_batched_dense if args.workload == "batched_dense" else bench_grad
-        print(json.dumps(fn(args, torch, Solver)), flush=True)
-        return
-    kind, inst, wl = make_workload(args.workload)
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    solver = Solver(device=dev)
-    solver.set_launch(args.workgroups, 0, args.tile)
-    b = torch.from_numpy(inst.b).to(dev)
-    if kind == "dense":
-        A = torch.from_numpy(inst.A).to(dev)
-        call = lambda: solver.solve(b, inst.tau, A=A)  # noqa: E731
-        n, m = inst.n, inst.m
-    else:
-        rows = torch.from_numpy(inst.rows).to(dev)
-        call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n)  # noqa: E731
-        n, m = inst.n, inst.m
-    if args.copy_calib_mb > 0:
-        src = torch.empty(args.copy_calib_mb << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
-    kms = []
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = call()
-        kms.append(r.kernel_ms)
-        infos.append(r.infos[0])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    info = infos[-1]
-    if info["status"] != 0:
-        print(f"bench.py: solve did not converge: {info}", file=sys.stderr)
-    ms_step = 1e3 * wall / args.steps
-    kms_mean = float(np.mean(kms))
-    ab = alg_bytes(kind, n, m, info)
-    achieved = ab / (kms_mean * 1e-3) / 1e9
-    out = {
-        "metric": METRIC,
-        "value": round(args.steps / wall, 3),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": wl, "n": n, "m": m, "tau": inst.tau, "tol": solver.params.tol,
-                   "tolpcg": solver.params.tolpcg, "ipm_iters": info["ipm_iters"],
-                   "pcg_iters": info["pcg_iters"], "correctors": info["correctors"], "nmat": info["nmat"],
-                   "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
-                   "kernel_ms_min": round(float(np.min(kms)), 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl),
-                     "kernel": "k_mfipm<OpPdct,0>" if kind == "pdct" else "k_mfipm<OpDense,0>",
-                     "alg_bytes_per_launch": ab},
-    }
-    solver.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(kind, inst, args.cpu_seconds)
+    fn = {"batched_dense": bench_batched_dense, "grad": bench_grad}.get(args.workload, bench_single)
+    out = fn(args, torch, Solver)
     print(json.dumps(out), flush=True)
 
 

@@ -64,6 +64,9 @@ extern "C" {
 #define MFIPM_STATUS_STEP_UNDERFLOW 4 /* both step sizes below step_min                     */
 #define MFIPM_STATUS_ABORTED 5        /* a device-side wait exceeded its bound              */
 #define MFIPM_STATUS_INPUT_CHECK 6    /* device-side input check failed (rows)              */
+#define MFIPM_STATUS_PCG_MAXITER 7    /* backward only: the adjoint PCG reached mxiterpcg_adj
+                                         before tolpcg_adj; the gradients are those of its
+                                         last iterate                                       */
 
 /* operator kinds */
 #define MFIPM_OP_DENSE 0 /* explicit m x n row-major matrix                                     */
@@ -173,7 +176,10 @@ int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, co
  * grad_b = A (w_u - w_v) (m doubles per instance) and grad_tau = -1^T w
  * (one double per instance, device).  Offsets/operator as in the batched
  * solve.  infos (HOST, may be NULL): status and pcg_iters of the adjoint
- * solve.  Errors: NO_STATE for a NULL state, else as mfipm_solve.            */
+ * solve: CONVERGED, PCG_MAXITER (cap reached; gradients of the last
+ * iterate), or PCG_BREAKDOWN / NONFINITE / ABORTED / INPUT_CHECK, in which
+ * case every grad_b entry and grad_tau of that instance are NaN.
+ * Errors: NO_STATE for a NULL state, else as mfipm_solve.                    */
 int mfipm_backward(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
                    const int64_t* a_off, int32_t op_kind, const double* A_packed,
                    const int32_t* rows_packed, int32_t shared_op, const double* state_packed,

@@ -14,6 +14,21 @@ import torch
 from .mfipm import Solver
 
 
+class SolveStatusError(RuntimeError):
+    """An instance of a forward or adjoint solve did not end with status 0."""
+
+    def __init__(self, where, bad):
+        super().__init__(f"{where}: instances not converged: {bad}")
+        self.where = where
+        self.bad = bad
+
+
+def _raise_on_status(where, infos):
+    bad = [(j, i["status_name"]) for j, i in enumerate(infos) if i["status"] != 0]
+    if bad:
+        raise SolveStatusError(where, bad)
+
+
 class MfipmSolve(torch.autograd.Function):
     """x = MfipmSolve.apply(b, tau, solver, A, rows, n) for a single instance,
     or a batch when b is 2-D (B x m) and tau is 1-D (B): all instances share
@@ -32,6 +47,7 @@ class MfipmSolve(torch.autograd.Function):
             taus = np.full(B, float(taus[0]))
         res = solver.solve_batched(bb.detach().reshape(-1), taus, n_off, m_off, A_packed=A, rows=rows,
                                    shared_op=True)
+        _raise_on_status("forward", res.infos)
         ctx.solver = solver
         ctx.A, ctx.rows = A, rows
         ctx.n_off, ctx.m_off = n_off, m_off
@@ -46,8 +62,9 @@ class MfipmSolve(torch.autograd.Function):
     def backward(ctx, grad_x):
         (state,) = ctx.saved_tensors
         g = grad_x if ctx.batched else grad_x.unsqueeze(0)
-        gb, gt, _ = ctx.solver.backward(state, g.contiguous().reshape(-1), ctx.n_off, ctx.m_off,
-                                        A_packed=ctx.A, rows=ctx.rows, shared_op=True)
+        gb, gt, binf = ctx.solver.backward(state, g.contiguous().reshape(-1), ctx.n_off, ctx.m_off,
+                                           A_packed=ctx.A, rows=ctx.rows, shared_op=True)
+        _raise_on_status("backward", binf)
         B = g.shape[0]
         gb = gb.view(B, -1)
         if not ctx.batched:

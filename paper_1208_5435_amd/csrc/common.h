@@ -19,6 +19,7 @@ enum {
   ST_STEP_UNDERFLOW = 4,
   ST_ABORTED = 5,
   ST_DEVICE_CHECK = 6,
+  ST_PCG_MAXITER = 7,  // adjoint only: PCG cap reached before its tolerance
 };
 
 struct cplx {

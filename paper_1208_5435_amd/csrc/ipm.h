@@ -748,7 +748,7 @@ __device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& a
 // ------------------------------------------------------------------------
 template <class OP>
 __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit,
-                                       double rhs2, double gamma, double yty, int* iters) {
+                                       double rhs2, double gamma, double yty, int* iters, int* capped = nullptr) {
   const int kB[1] = {0};
   const int kC[5] = {0, 0, 0, 0, 0};
   double rr = rhs2, beta = 0.0, ptp = yty;
@@ -759,7 +759,10 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
       break;
     }
     if (rr <= tol * tol * rhs2) break;
-    if (it == maxit) break;
+    if (it == maxit) {
+      if (capped) *capped = 1;
+      break;
+    }
     const int first = (it == 0);
     op_direction(op, w, it);
     run_B<OP>(cx, op, 0, w.partB, nullptr, beta, first);
@@ -1069,7 +1072,7 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
   const long n = d.n;
   const double2* Z = (const double2*)(a.state + 4 * d.n_off);
   const double2* S = (const double2*)(a.state + 4 * d.n_off + 2 * d.n);
-  int status = 0, its = 0;
+  int status = 0, its = 0, capped = 0;
   double rho = prm.rho, gtau = 0.0;
   int st = op_setup(cx, op, a, w, 0);
   if (st) status = st;
@@ -1092,9 +1095,9 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
     if (team_barrier(cx.t)) st = ST_ABORTED;
     double pI[3];
     reduce_items<3>(kI, w.partA, op.nA(), pI, cx.red);
-    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its);
+    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its, &capped);
     status = st;
-    if (!st || st == ST_PCG_BREAKDOWN) {
+    if (!st) {
       FBwdGather fg;
       fg.W = w.X;
       const int kG[1] = {0};
@@ -1108,7 +1111,17 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
         if (team_barrier(cx.t)) status = ST_ABORTED;
         if (!status) op_forward_gather(cx, op, w, a.grad_b + d.m_off);
       }
+      // the adjoint system was not solved to its tolerance: the gradients
+      // are those of the last PCG iterate, flagged by the status
+      if (!status && capped) status = ST_PCG_MAXITER;
     }
+  }
+  if (status && status != ST_PCG_MAXITER) {
+    // no gradient: NaN in every output of the instance
+    const long nthr = (long)cx.t.size * MF_THREADS;
+    double* gb = a.grad_b + d.m_off;
+    for (long i = (long)cx.t.rank * MF_THREADS + threadIdx.x; i < d.m; i += nthr) gb[i] = __builtin_nan("");
+    gtau = __builtin_nan("");
   }
   if (cx.t.rank == 0 && threadIdx.x == 0) {
     a.grad_tau[ii] = gtau;

@@ -391,15 +391,25 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   });
   hipStream_t s = h->stream;
   std::memcpy(desc + (size_t)P.batch * sizeof(InstDesc), order.data(), sizeof(int) * P.batch);
-  HIP_TRY(hipMemcpyAsync(base + gl.inst, desc, desc_bytes, hipMemcpyHostToDevice, s));
+  if (hipMemcpyAsync(base + gl.inst, desc, desc_bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    return MFIPM_ERR_HIP;
+  }
+  // From here on the staging buffer may still be read by the copy engine:
+  // every return waits for the stream first, so the next call can reuse it.
+  auto fail = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    return code;
+  };
   const int logn_max = ilog2_host(P.n_max);
   const cplx* tw = nullptr;
   if (P.op_kind == MFIPM_OP_PDCT) {
     tw = twiddle_tables(h, logn_max + 2, gl.lo_bits);
-    if (!tw) return MFIPM_ERR_HIP;
+    if (!tw) return fail(MFIPM_ERR_HIP);
   }
   // zero the control words: queue head, abort flag, team barriers and slots
-  HIP_TRY(hipMemsetAsync(base + gl.ctl, 0, 256 + (size_t)num_teams * MF_CTL_BYTES, s));
+  if (hipMemsetAsync(base + gl.ctl, 0, 256 + (size_t)num_teams * MF_CTL_BYTES, s) != hipSuccess)
+    return fail(MFIPM_ERR_HIP);
 
   KArgs a{};
   a.inst = (const InstDesc*)(base + gl.inst);
@@ -431,15 +441,17 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
 
   void* args[] = {&a};
   const int grid = num_teams * team_size;
-  HIP_TRY(hipEventRecord(h->ev0, s));
+  if (hipEventRecord(h->ev0, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
   if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd), dim3(grid), dim3(MF_THREADS), args,
                                  (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
-    return MFIPM_ERR_HIP;
-  HIP_TRY(hipEventRecord(h->ev1, s));
+    return fail(MFIPM_ERR_HIP);
+  if (hipEventRecord(h->ev1, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
   const DevInfo* dinf = reinterpret_cast<const DevInfo*>(h->pinned);
   const int* ctl = reinterpret_cast<const int*>(h->pinned + align_up((size_t)P.batch * sizeof(DevInfo)));
-  HIP_TRY(hipMemcpyAsync(h->pinned, base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((void*)ctl, base + gl.ctl, 128, hipMemcpyDeviceToHost, s));
+  if (hipMemcpyAsync(h->pinned, base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync((void*)ctl, base + gl.ctl, 128, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(MFIPM_ERR_HIP);
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
@@ -623,6 +635,7 @@ const char* mfipm_status_string(int32_t code) {
     case MFIPM_STATUS_STEP_UNDERFLOW: return "step underflow";
     case MFIPM_STATUS_ABORTED: return "aborted (device wait bound exceeded)";
     case MFIPM_STATUS_INPUT_CHECK: return "input check failed";
+    case MFIPM_STATUS_PCG_MAXITER: return "adjoint PCG iteration limit";
     default: return "unknown";
   }
 }

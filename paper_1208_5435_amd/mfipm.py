@@ -6,8 +6,11 @@ binding fails loudly when the built library is missing; there is no CPU path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -19,7 +22,7 @@ OP_DENSE = 0
 OP_PDCT = 1
 
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "PCG_BREAKDOWN", 3: "NONFINITE", 4: "STEP_UNDERFLOW",
-          5: "ABORTED", 6: "INPUT_CHECK"}
+          5: "ABORTED", 6: "INPUT_CHECK", 7: "PCG_MAXITER"}
 ERRORS = {-1: "INVALID_ARG", -2: "HIP_ERROR", -3: "WORKSPACE_TOO_SMALL", -4: "NO_STATE",
           -5: "DEVICE_CHECK"}
 
@@ -62,6 +65,18 @@ class Operator(ctypes.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()  # open Solver handles, closed at interpreter exit
+
+
+@atexit.register
+def _close_all():
+    """Releases every open handle while the HIP runtime is still up (before
+    module teardown), after the device has finished its work."""
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
 
 
 def load_library(path: str | None = None):
@@ -152,17 +167,25 @@ class Solver:
             _check("mfipm_create", self.lib.mfipm_create(ctypes.byref(h), ctypes.byref(prm),
                                                          ctypes.c_void_p(self.stream.cuda_stream)))
         self.h = h
+        _live.add(self)
         self._ws = None
         self._explicit = None  # launch shape fixed by the caller
         self.arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         self.num_cu = torch.cuda.get_device_properties(self.device).multi_processor_count
 
     def close(self):
+        """Waits for the handle's stream, then releases the handle."""
         if getattr(self, "h", None):
+            self.stream.synchronize()
             self.lib.mfipm_destroy(self.h)
             self.h = None
+            self._ws = None
 
     def __del__(self):
+        # At interpreter shutdown the runtime may already be gone; the exit
+        # handler above has closed every handle by then.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -11,6 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU test (large oracle solves)")
+    # the oracle's host worker server starts before any test touches the GPU
+    from oracle import pool
+    pool.start()
 
 
 @pytest.fixture(scope="session")

@@ -1,15 +1,33 @@
-"""Helpers shared by the GPU parity tests (comparison against the oracle)."""
+"""Parity gates of the GPU tests against the CPU oracle.
+
+The bar: ||x_gpu - x_cpu|| / ||x_cpu|| <= 1e-6 at the test's IPM tolerance
+(1e-8 unless stated), KKT residual <= 1e-6, identical status and IPM
+iteration counts within +-1.
+
+Two escalations exist, each printed on its own line and recorded in
+`EVENTS`:
+  * x: when the GPU and oracle points differ by more than 1e-6 at the test
+    tolerance, both sides are solved again at tolerance 1e-12 (PCG 1e-8) and
+    must agree to 1e-6 there;
+  * KKT: when the oracle's own point misses KKT <= 1e-6 at the test tolerance
+    (small instances whose objective is small, where the relative gap
+    (P - D)/(1 + |P|) is in effect an absolute gap), both sides are solved at
+    tolerance 1e-12 and the GPU must meet 1e-6 wherever the oracle does
+    there; if even the oracle's tight point misses it, the GPU's tight point
+    may be no worse than twice the oracle's.
+`strict=True` (the full-size workloads) allows no escalation.
+"""
 from __future__ import annotations
 
 import numpy as np
 
 from oracle import mfipm_ref as R
 
-# Parity bar: ||x_gpu - x_cpu|| / ||x_cpu|| <= 1e-6 at IPM tol 1e-8, KKT <= 1e-6,
-# IPM iteration counts within +-1 of the oracle.
 X_REL = 1e-6
 KKT_TOL = 1e-6
 ITER_SLACK = 1
+TIGHT = dict(tol=1e-12, tolpcg=1e-8, mxiterpcg=2000)
+EVENTS: list = []
 
 
 def rel(a, b):
@@ -17,35 +35,101 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
 
 
-def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label=""):
-    """Runs the oracle on the same inputs and applies the parity bar."""
-    ref = R.solve(op, b, tau, params)
+def zs_from_state(st, n):
+    """Interleaved (u, v) pairs of the library's state -> z = [u; v], s = [s_u; s_v]."""
+    st = np.asarray(st)
+    z = st[: 2 * n].reshape(n, 2).T.reshape(-1)
+    s = st[2 * n: 4 * n].reshape(n, 2).T.reshape(-1)
+    return z, s
+
+
+def kkt_of(op, b, tau, x, z, s):
+    S, sg = R.support_from_state(z, s, op.n)
+    return R.kkt_residual(op, b, tau, x, S, sg)
+
+
+def _event(msg):
+    EVENTS.append(msg)
+    print(msg, flush=True)
+
+
+def resolver(solver, **solve_kwargs):
+    """GPU re-solve of one instance under other parameters (single-instance
+    entry point); returns (x, state) as numpy arrays."""
+    def run(prm):
+        old = {k: getattr(solver.params, k) for k in prm}
+        solver.set_params(**prm)
+        try:
+            r = solver.solve(**solve_kwargs)
+        finally:
+            solver.set_params(**old)
+        return r.x.cpu().numpy(), r.state.cpu().numpy()
+    return run
+
+
+def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label="", resolve=None,
+                         strict=False, ref=None):
+    """Runs the oracle on the same inputs (unless `ref` is given) and applies
+    the parity bar.  `state`: the GPU's final (z, s) (library layout), used
+    for the GPU's support in the KKT residual.  `resolve(prm)` re-solves the
+    instance on the GPU under `prm` (needed for an escalation)."""
+    if ref is None:
+        ref = R.solve(op, b, tau, params)
     assert info["status"] == ref.status, (label, info, R.STATUS_NAMES[ref.status])
     assert abs(info["ipm_iters"] - ref.ipm_iters) <= ITER_SLACK, (label, info["ipm_iters"], ref.ipm_iters)
     xg = np.asarray(x_gpu)
-    if np.max(np.abs(ref.x)) <= 1e-8 * (1 + np.max(np.abs(b))):
+    n = op.n
+    tight = {}
+
+    def tight_pair():
+        if not tight:
+            assert resolve is not None, (label, "escalation needs a GPU re-solve")
+            xt, st = resolve(TIGHT)
+            tight["gpu"] = (xt, st)
+            tight["ref"] = R.solve(op, b, tau, R.Params(**TIGHT))
+        return tight["gpu"], tight["ref"]
+
+    bscale = 1.0 + float(np.max(np.abs(b)))
+    if np.max(np.abs(ref.x)) <= 1e-8 * bscale:
         # degenerate x* = 0: absolute gate
-        assert np.max(np.abs(xg)) <= 1e-8 * (1 + np.max(np.abs(b))), label
-    elif rel(xg, ref.x) > X_REL:
-        # The gap test only fixes x to O(gap): when the objective is tiny the
-        # tolerance leaves x loose.  Then both answers are compared with a
-        # tightly converged oracle solution; the GPU's may be no farther from
-        # it than twice the oracle's own distance (plus the bar).
-        tight = R.solve(op, b, tau, R.Params(tol=1e-12, tolpcg=1e-8, mxiterpcg=2000))
-        d_ref = rel(ref.x, tight.x)
-        d_gpu = rel(xg, tight.x)
-        assert d_ref > X_REL / 10, (label, "tolerance determines x, yet GPU differs", rel(xg, ref.x))
-        assert d_gpu <= 2 * d_ref + X_REL, (label, d_gpu, d_ref)
-    if ref.status == R.CONVERGED:
-        if state is not None:
-            n = op.n
-            st = np.asarray(state)
-            z = st[: 2 * n].reshape(n, 2).T.reshape(-1)   # interleaved (u,v) -> [u; v]
-            s = st[2 * n:].reshape(n, 2).T.reshape(-1)
-            S, sg = R.support_from_state(z, s, n)
-        else:
-            S, sg = R.support_from_state(ref.z, ref.s, op.n)
-        kkt = R.kkt_residual(op, b, tau, xg, S, sg)
-        kkt_ref = R.kkt_residual(op, b, tau, ref.x, *R.support_from_state(ref.z, ref.s, op.n))
-        assert kkt <= max(KKT_TOL, 10 * kkt_ref), (label, kkt, kkt_ref)
+        assert np.max(np.abs(xg)) <= 1e-8 * bscale, label
+        return ref
+    r = rel(xg, ref.x)
+    if r > X_REL:
+        _event(f"PARITY-ESCALATION x {label}: rel(x) = {r:.2e} at tol {ref_tol(params)}; "
+               f"comparing at tol {TIGHT['tol']}")
+        assert not strict, (label, "strict gate", r)
+        (xt, _), rt = tight_pair()
+        r_t = rel(xt, rt.x)
+        print(f"    tight rel(x) = {r_t:.2e}", flush=True)
+        assert r_t <= X_REL, (label, r_t)
+    if ref.status != R.CONVERGED:
+        return ref
+    kkt_ref = kkt_of(op, b, tau, ref.x, ref.z, ref.s)
+    if state is not None:
+        zg, sg_ = zs_from_state(state, n)
+    else:
+        zg, sg_ = ref.z, ref.s
+    kkt_gpu = kkt_of(op, b, tau, xg, zg, sg_)
+    if kkt_ref <= KKT_TOL:
+        assert kkt_gpu <= KKT_TOL, (label, kkt_gpu, kkt_ref)
+        return ref
+    _event(f"PARITY-ESCALATION kkt {label}: oracle KKT {kkt_ref:.2e} > {KKT_TOL} at tol {ref_tol(params)} "
+           f"(GPU {kkt_gpu:.2e}); comparing at tol {TIGHT['tol']}")
+    assert not strict, (label, "strict gate", kkt_ref)
+    (xt, stt), rt = tight_pair()
+    zt, st_ = zs_from_state(stt, n)
+    kg_t = kkt_of(op, b, tau, xt, zt, st_)
+    kr_t = kkt_of(op, b, tau, rt.x, rt.z, rt.s)
+    print(f"    tight KKT: GPU {kg_t:.2e} oracle {kr_t:.2e}", flush=True)
+    if kr_t <= KKT_TOL:
+        assert kg_t <= KKT_TOL, (label, kg_t, kr_t)
+    else:
+        _event(f"PARITY-ESCALATION kkt {label}: oracle misses KKT {KKT_TOL} even at tol {TIGHT['tol']} "
+               f"({kr_t:.2e}); GPU {kg_t:.2e} gated at twice that")
+        assert kg_t <= 2.0 * kr_t, (label, kg_t, kr_t)
     return ref
+
+
+def ref_tol(params):
+    return (params.tol if params is not None else R.Params().tol)

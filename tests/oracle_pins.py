@@ -163,3 +163,54 @@ def pin_gradient(A, b, tau, x_true):
     eb = np.linalg.norm(gr.grad_b - gb_cf) / np.linalg.norm(gb_cf)
     et = abs(gr.grad_tau - gt_cf) / abs(gt_cf)
     return max(eb, et)
+
+
+def pin_rho(op, b, tau):
+    """The preconditioner scalar the solver uses against the paper's
+    criterion, found by a one-dimensional search rather than a formula: rho is
+    the multiple of the identity closest to A^T A in the Frobenius norm
+    (Section 4, before eq. (eq:ne2_P)).  For orthonormal rows (partial DCT)
+    this is m/n.  ||A^T A - r I||_F^2 is a parabola in r, so its minimiser is
+    the vertex through three evaluations of the distance itself (explicit A).
+    Returns the relative distance of the solver's rho from that vertex."""
+    res = R.solve(op, b, tau, R.Params(maxiters=1))
+    A = op.dense()
+    K = A.T @ A
+    f = [float(np.linalg.norm(K - r * np.eye(op.n)) ** 2) for r in (0.0, 1.0, 2.0)]
+    a2 = (f[2] - 2.0 * f[1] + f[0]) / 2.0
+    a1 = f[1] - f[0] - a2
+    vertex = -a1 / (2.0 * a2)
+    return abs(res.rho - vertex) / vertex
+
+
+def pin_kkt_handbuilt():
+    """kkt_residual on points with a known answer.  With A = I the gradient
+    of the least-squares term is g = x - b.  Case 1: x = soft(b, tau) is the
+    minimiser, residual 0.  Case 2: entry j off the support with
+    |b_j| = tau (1 + eps): residual eps.  Case 3: a support entry moved by
+    delta: |g_j + tau sign x_j| = delta, residual delta / tau.  Case 4: a
+    support entry with the wrong sign of g: residual 2.  Returns the largest
+    deviation from the known values."""
+    n, tau = 16, 0.5
+    rng = rng_for(13)
+    b = rng.standard_normal(n) * 2.0
+    b[np.abs(b) < 0.7] += 1.0  # keep entries away from the threshold
+    b[0], b[1] = 0.1, -0.2    # two entries off the support
+    op = R.DenseOperator(np.eye(n))
+    x = R.soft_threshold(b, tau)
+    S = np.nonzero(x)[0]
+    sg = np.sign(x[S])
+    errs = [abs(R.kkt_residual(op, b, tau, x, S, sg) - 0.0)]
+    eps = 0.25
+    b2 = b.copy()
+    b2[0] = tau * (1 + eps)          # x_0 = 0 stays, so |g_0| = tau (1 + eps)
+    errs.append(abs(R.kkt_residual(op, b2, tau, x, S, sg) - eps))
+    delta = 1e-3
+    x3 = x.copy()
+    j = S[0]
+    x3[j] += delta
+    errs.append(abs(R.kkt_residual(op, b, tau, x3, S, sg) - delta / tau))
+    sg4 = sg.copy()
+    sg4[0] = -sg4[0]
+    errs.append(abs(R.kkt_residual(op, b, tau, x, S, sg4) - 2.0))
+    return max(errs)

@@ -43,7 +43,8 @@ def test_batched_dense_uneven(solver):
     st = res.state.cpu().numpy()
     for j, inst in enumerate(insts):
         U.check_against_oracle(R.DenseOperator(inst.A), inst.b, inst.tau, x[n_off[j]:n_off[j + 1]],
-                               res.infos[j], st[4 * n_off[j]:4 * n_off[j + 1]], label=f"batch dense {j}")
+                               res.infos[j], st[4 * n_off[j]:4 * n_off[j + 1]], label=f"batch dense {j}",
+                               resolve=U.resolver(solver, b=inst.b, tau=inst.tau, A=inst.A))
 
 
 def test_batched_equals_single_bitwise(solver):
@@ -73,9 +74,12 @@ def test_batched_pdct_uneven_lengths(solver):
     b = np.concatenate([i.b for i in insts])
     res = solver.solve_batched(b, [i.tau for i in insts], n_off, m_off, rows=rows)
     x = res.x.cpu().numpy()
+    st = res.state.cpu().numpy()
     for j, inst in enumerate(insts):
         U.check_against_oracle(R.PartialDCTOperator(inst.n, inst.rows), inst.b, inst.tau,
-                               x[n_off[j]:n_off[j + 1]], res.infos[j], label=f"batch pdct {j}")
+                               x[n_off[j]:n_off[j + 1]], res.infos[j], st[4 * n_off[j]:4 * n_off[j + 1]],
+                               label=f"batch pdct {j}",
+                               resolve=U.resolver(solver, b=inst.b, tau=inst.tau, rows=inst.rows, n=inst.n))
 
 
 def test_batched_pdct_shared_rows(solver):
@@ -86,16 +90,19 @@ def test_batched_pdct_shared_rows(solver):
     m_off = np.arange(B + 1, dtype=np.int64) * m
     res = solver.solve_batched(inst.b.reshape(-1), inst.tau, n_off, m_off, rows=inst.rows, shared_op=True)
     x = res.x.cpu().numpy()
+    st = res.state.cpu().numpy()
     op = R.PartialDCTOperator(inst.n, inst.rows)
     for j in range(B):
         U.check_against_oracle(op, inst.b[j], inst.tau[j], x[n_off[j]:n_off[j + 1]], res.infos[j],
-                               label=f"shared {j}")
+                               st[4 * n_off[j]:4 * n_off[j + 1]], label=f"shared {j}",
+                               resolve=U.resolver(solver, b=inst.b[j], tau=inst.tau[j], rows=inst.rows,
+                                                  n=inst.n))
 
 
-def test_batched_dense_sampled_large(solver):
-    """A scaled batch of the uneven dense workload (n multiple of 64 in
-    [1024, 8192]); three sampled instances against the oracle, every instance
-    against its own gap certificate."""
+def test_batched_dense_12_of_workload(solver):
+    """The first 12 instances of the uneven dense workload (n multiple of 64
+    in [1024, 8192]) in one launch: every instance against its own gap
+    certificate and against the oracle at the strict bar."""
     sizes = W.batched_dense_sizes(batch=12)
     insts = [W.batched_dense_instance(i, int(n)) for i, n in enumerate(sizes)]
     say("batched dense sampled", list(sizes))
@@ -114,10 +121,12 @@ def test_batched_dense_sampled_large(solver):
         _, r, g, primal = R.objective_terms(op, inst.b, inst.tau, z)
         gap, _ = R.relative_gap(inst.b, inst.tau, r, g, primal)
         assert gap <= 1e-7, (j, gap)
-    for j in (0, 5, 11):
+    st = res.state.cpu().numpy()
+    for j in range(len(insts)):
         inst = insts[j]
         U.check_against_oracle(R.DenseOperator(inst.A), inst.b, inst.tau, x[n_off[j]:n_off[j + 1]],
-                               res.infos[j], label=f"sampled {j}")
+                               res.infos[j], st[4 * n_off[j]:4 * n_off[j + 1]], label=f"batch12 {j}",
+                               strict=True)
 
 
 # ---------------------------------------------------------------- adjoint --------

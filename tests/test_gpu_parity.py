@@ -37,7 +37,8 @@ def test_dense_small(solver, m, n, k, seed):
     inst = _dense(m, n, k, seed)
     res = solver.solve(inst.b, inst.tau, A=inst.A)
     U.check_against_oracle(R.DenseOperator(inst.A), inst.b, inst.tau, res.x.cpu().numpy(), res.infos[0],
-                           res.state.cpu().numpy(), label=f"dense{m}x{n}")
+                           res.state.cpu().numpy(), label=f"dense{m}x{n}",
+                           resolve=U.resolver(solver, b=inst.b, tau=inst.tau, A=inst.A))
 
 
 def test_dense_256x1024(solver):
@@ -45,7 +46,7 @@ def test_dense_256x1024(solver):
     inst = W.config_dense_256x1024()
     res = solver.solve(inst.b, inst.tau, A=inst.A)
     ref = U.check_against_oracle(R.DenseOperator(inst.A), inst.b, inst.tau, res.x.cpu().numpy(),
-                                 res.infos[0], res.state.cpu().numpy(), label="C1")
+                                 res.infos[0], res.state.cpu().numpy(), label="C1", strict=True)
     say("  gpu", res.infos[0], "oracle iters", ref.ipm_iters, ref.pcg_iters)
 
 
@@ -56,7 +57,8 @@ def test_pdct_small(solver, n, m, k, seed):
     inst = W.dct_instance(n, m, k, seed=seed, amp="normal", sigma=1e-2, c_tau=1e-2)
     res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=n)
     U.check_against_oracle(R.PartialDCTOperator(n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(),
-                           res.infos[0], res.state.cpu().numpy(), label=f"pdct{n}/{m}")
+                           res.infos[0], res.state.cpu().numpy(), label=f"pdct{n}/{m}",
+                           resolve=U.resolver(solver, b=inst.b, tau=inst.tau, rows=inst.rows, n=n))
 
 
 @pytest.mark.parametrize("l1", [2, 4, 6])
@@ -71,7 +73,8 @@ def test_pdct_tile_choices(solver, l1):
     finally:
         solver.set_launch(0, 0, 0)
     U.check_against_oracle(R.PartialDCTOperator(n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(),
-                           res.infos[0], label=f"l1={l1}")
+                           res.infos[0], res.state.cpu().numpy(), label=f"l1={l1}",
+                           resolve=U.resolver(solver, b=inst.b, tau=inst.tau, rows=inst.rows, n=n))
 
 
 def test_pdct_2p16(solver):
@@ -79,7 +82,8 @@ def test_pdct_2p16(solver):
     inst = W.config_pdct()
     res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n)
     ref = U.check_against_oracle(R.PartialDCTOperator(inst.n, inst.rows), inst.b, inst.tau,
-                                 res.x.cpu().numpy(), res.infos[0], res.state.cpu().numpy(), label="C2")
+                                 res.x.cpu().numpy(), res.infos[0], res.state.cpu().numpy(), label="C2",
+                                 strict=True)
     say("  gpu", res.infos[0], "oracle", ref.ipm_iters, ref.pcg_iters, "ms", res.kernel_ms)
 
 

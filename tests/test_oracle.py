@@ -203,3 +203,26 @@ def test_status_maxiter_and_nonfinite():
     bb[0] = np.nan
     r = R.solve(op, bb, tau)
     assert r.status == R.NONFINITE
+
+
+@pytest.mark.parametrize("kind", ["dense", "dct", "scaled"])
+def test_rho_is_frobenius_closest(kind):
+    rng = PIN.rng_for(41)
+    n = 48
+    if kind == "dense":
+        A, b, tau, _ = PIN.dense_problem(12, n, 2, seed=41)
+        op = R.DenseOperator(A)
+    elif kind == "scaled":  # rows far from orthonormal: rho must follow ||A||_F
+        A, b, tau, _ = PIN.dense_problem(12, n, 2, seed=42)
+        op = R.DenseOperator(3.0 * A)
+    else:
+        op = R.PartialDCTOperator(n, np.sort(rng.choice(n, 12, replace=False)))
+        b = rng.standard_normal(12)
+        tau = 0.1
+    assert PIN.pin_rho(op, b, tau) <= 1e-9
+    if kind == "dct":
+        assert R.solve(op, b, tau, R.Params(maxiters=1)).rho == 12 / n
+
+
+def test_kkt_residual_handbuilt():
+    assert PIN.pin_kkt_handbuilt() <= 1e-12

@@ -136,3 +136,59 @@ def test_parameter_slip_caught(field, value):
     with open(os.path.join(os.path.dirname(__file__), "golden", "paper_params.json")) as f:
         gold = json.load(f)["values"]
     assert gold[field]["value"] != value
+
+
+def test_rho_denominator_slip_caught(monkeypatch):
+    """rho = ||A||_F^2 / m instead of / n."""
+    def bad_frob2(self):
+        return float(np.sum(self.A * self.A)) * self.n / self.m
+    monkeypatch.setattr(R.DenseOperator, "frob2", bad_frob2)
+    A, b, tau, _ = PIN.dense_problem(12, 48, 2, seed=41)
+    assert PIN.pin_rho(R.DenseOperator(A), b, tau) > 1e-3
+
+
+def test_rho_unsquared_slip_caught(monkeypatch):
+    """Frobenius norm instead of its square."""
+    def bad_frob2(self):
+        return float(np.sqrt(np.sum(self.A * self.A)))
+    monkeypatch.setattr(R.DenseOperator, "frob2", bad_frob2)
+    A, b, tau, _ = PIN.dense_problem(12, 48, 2, seed=42)
+    assert PIN.pin_rho(R.DenseOperator(3.0 * A), b, tau) > 1e-3
+
+
+def test_rho_dct_slip_caught(monkeypatch):
+    """A partial DCT whose rho ignores the sampled rows (rho = 1)."""
+    monkeypatch.setattr(R.PartialDCTOperator, "frob2", lambda self: float(self.n))
+    rng = PIN.rng_for(41)
+    op = R.PartialDCTOperator(48, np.sort(rng.choice(48, 12, replace=False)))
+    assert PIN.pin_rho(op, rng.standard_normal(12), 0.1) > 1e-3
+
+
+def _kkt_no_offsupport(op, b, tau, x, support=None, signs=None):
+    g = op.rmatvec(op.matvec(x) - b)
+    on = float(np.max(np.abs(g[support] + tau * signs))) if len(support) else 0.0
+    return on / tau                     # slip: dropped the |g_i| <= tau term
+
+
+def _kkt_sign(op, b, tau, x, support=None, signs=None):
+    g = op.rmatvec(op.matvec(x) - b)
+    viol = float(np.max(np.maximum(np.abs(g) - tau, 0.0)))
+    on = float(np.max(np.abs(g[support] - tau * signs))) if len(support) else 0.0   # slip: sign
+    return max(viol, on) / tau
+
+
+def _kkt_unscaled(op, b, tau, x, support=None, signs=None):
+    g = op.rmatvec(op.matvec(x) - b)
+    viol = float(np.max(np.maximum(np.abs(g) - tau, 0.0)))
+    on = float(np.max(np.abs(g[support] + tau * signs))) if len(support) else 0.0
+    return max(viol, on)                 # slip: not relative to tau
+
+
+def _kkt_zero(op, b, tau, x, support=None, signs=None):
+    return 0.0                           # slip: a residual that never reports
+
+
+@pytest.mark.parametrize("bad", [_kkt_no_offsupport, _kkt_sign, _kkt_unscaled, _kkt_zero])
+def test_kkt_residual_slip_caught(monkeypatch, bad):
+    monkeypatch.setattr(R, "kkt_residual", bad)
+    assert PIN.pin_kkt_handbuilt() > 1e-3

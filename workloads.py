@@ -33,7 +33,7 @@ __all__ = [
     "DenseInstance", "DCTInstance", "dense_instance", "dct_instance",
     "config_dense_256x1024", "config_pdct", "config_pdct_hdr",
     "batched_dense_sizes", "batched_dense_instance", "config_dct_batch",
-    "dct_apply", "dct_apply_t",
+    "dct_apply", "dct_apply_t", "SharedDenseInstance", "config_shared_dense",
 ]
 
 
@@ -172,3 +172,45 @@ def config_dct_batch(n: int = 1 << 18, batch: int = 32, seed: int = 120805,
     direction /= np.linalg.norm(direction, axis=1, keepdims=True)
     return DCTInstance(n=n, rows=rows, b=Bm, tau=taus, x_true=X, seed=seed,
                        label=f"pdct_batch{batch}_n{n}", extra={"fd_direction": direction})
+
+
+def config_shared_dense(m: int = 2048, n: int = 8192, batch: int = 256, seed: int = 120806,
+                        signals=None) -> "SharedDenseInstance":
+    """`batch` signals observed through ONE dense Gaussian A (m x n, i.i.d.
+    N(0, 1/m)): k = floor(n/50) N(0,1) spikes, noise sigma = 1e-3,
+    tau = 1e-2 ||A^T b||_inf per signal.  A comes from PCG64(seed); signal j
+    from PCG64(seed * 1000 + j) (support -> amplitudes -> noise), so any
+    subset `signals` can be drawn alone."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    A = np.ascontiguousarray(rng.standard_normal((m, n)) / np.sqrt(m))
+    idx = list(range(batch)) if signals is None else list(signals)
+    k = n // 50
+    X = np.zeros((len(idx), n))
+    Bm = np.zeros((len(idx), m))
+    taus = np.zeros(len(idx))
+    for r, j in enumerate(idx):
+        srng = np.random.default_rng(np.random.PCG64(seed * 1000 + j))
+        X[r] = _sparse_signal(srng, n, k, "normal")
+        Bm[r] = A @ X[r] + 1e-3 * srng.standard_normal(m)
+        taus[r] = 1e-2 * np.max(np.abs(A.T @ Bm[r]))
+    return SharedDenseInstance(A=A, b=Bm, tau=taus, x_true=X, seed=seed, signals=idx,
+                               label=f"shared_dense_{batch}_m{m}_n{n}")
+
+
+@dataclass
+class SharedDenseInstance:
+    A: np.ndarray          # (m, n), shared by every signal
+    b: np.ndarray          # (B, m)
+    tau: np.ndarray        # (B,)
+    x_true: np.ndarray     # (B, n)
+    seed: int
+    signals: list
+    label: str = ""
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
