@@ -425,6 +425,56 @@ def bench_grad(args, torch, Solver):
     return out
 
 
+def bench_shared_dense(args, torch, Solver):
+    """256 signals sharing one 2048 x 8192 dense A in one lock-step launch
+    (operator = two FP64 MFMA matrix products per round), against one launch
+    per signal on the same A."""
+    import workloads as W
+    B = args.batch
+    inst = W.config_shared_dense(batch=B)
+    dev = torch.device("cuda", 0)
+    m, n = inst.m, inst.n
+    n_off = np.arange(B + 1, dtype=np.int64) * n
+    m_off = np.arange(B + 1, dtype=np.int64) * m
+    A = torch.from_numpy(inst.A).to(dev)
+    b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
+    solver = Solver(device=dev)
+    try:
+        solver.set_launch(args.workgroups, 0, 0)
+        run = lambda: solver.solve_batched(b, inst.tau, n_off, m_off, A_packed=A, shared_op=True)  # noqa: E731
+        _calibration_copy(args, torch, dev)
+        wall, kms, r = _timed(run, args, torch)
+        plain = None
+        if not args.no_plain:
+            solver.set_launch(0, 0, 0)
+            t1 = time.perf_counter()
+            for j in range(B):
+                solver.solve(b[j * m:(j + 1) * m], float(inst.tau[j]), A=A)
+            torch.cuda.synchronize()
+            plain = time.perf_counter() - t1
+    finally:
+        solver.close()
+    infos = r.infos
+    kms_mean = float(np.mean(kms))
+    flops = sum(2.0 * m * n * i["nmat"] for i in infos)  # each product with A or A^T: 2 m n
+    achieved = flops / (kms_mean * 1e-3) / 1e12
+    value = B * args.steps / wall
+    wl = f"shared_dense_{B}_m{m}_n{n}"
+    cfg = {"workload": wl, "batch": B, "m": m, "n": n, "kernel_ms_mean": round(kms_mean, 3),
+           "not_converged": [j for j, i in enumerate(infos) if i["status"] != 0],
+           "ipm_iters": [min(i["ipm_iters"] for i in infos), max(i["ipm_iters"] for i in infos)],
+           "nmat_max": max(i["nmat"] for i in infos), "nmat_sum": sum(i["nmat"] for i in infos)}
+    if plain:
+        cfg.update({"plain_solves_per_s": round(B / plain, 3), "batched_over_plain": round(value / (B / plain), 3)})
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": counter_traffic(wl),
+            "kernel": "k_mfipm_lockstep", "alg_flops_per_launch": flops}
+    out = _line(round(value, 3), "solves/s", args, 1e3 * wall / args.steps, cfg, roof)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_shared_dense(B, 16)
+    return out
+
+
 def tune_workload(args, torch, Solver):
     """Autotunes the launch shape of one workload (forward, and backward for
     the gradient batch) and writes it to the package's shipped table."""
@@ -485,7 +535,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched_dense",
-                    choices=["batched_dense", "pdct_hdr", "grad", "pdct", "dense"])
+                    choices=["batched_dense", "pdct_hdr", "grad", "shared_dense", "pdct", "dense"])
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--grad-n", type=int, default=1 << 18)
     ap.add_argument("--team", type=int, default=0)
@@ -525,7 +575,8 @@ def main():
     if args.tune:
         tune_workload(args, torch, Solver)
         return
-    fn = {"batched_dense": bench_batched_dense, "grad": bench_grad}.get(args.workload, bench_single)
+    fn = {"batched_dense": bench_batched_dense, "grad": bench_grad,
+          "shared_dense": bench_shared_dense}.get(args.workload, bench_single)
     out = fn(args, torch, Solver)
     print(json.dumps(out), flush=True)
 

@@ -4,16 +4,16 @@
  *
  * Problem (Fountoulakis, Gondzio, Zhlobich, "Matrix-free interior point method
  * for compressed sensing problems", Section 1 eq. (formulationsnoisy1) with the
- * 1/2 of Section 2 eq. (wrightBPDN)):
+ * 1/2 of Section 1 eq. (wrightBPDN)):
  *
  *     min_x  tau * ||x||_1 + 1/2 * ||A x - b||_2^2
  *
  * solved as the bound-constrained QP over z = [u; v] >= 0, x = u - v
- * (Section 2, eqs. (uvDef), (lintechni), (wrightBPDN)) by the single-corrector
- * primal-dual IPM of Section 7.1, whose Newton directions come from the
- * reduced system (Theta^{-1} + F F^T) dz = f_z + Z^{-1} f_s (Section 4,
+ * (Section 1, eqs. (uvDef), (lintechni), (wrightBPDN)) by the single-corrector
+ * primal-dual IPM of Section 5.1, whose Newton directions come from the
+ * reduced system (Theta^{-1} + F F^T) dz = f_z + Z^{-1} f_s (Section 3,
  * eq. (redNewton)) solved by preconditioned CG with the block preconditioner
- * of Section 5, eq. (eq:ne2_P).  A is only applied as A*d and A^T*y.
+ * of Section 4, eq. (eq:ne2_P).  A is only applied as A*d and A^T*y.
  *
  * Conventions for every entry point
  *   - All numeric data are IEEE double (FP64); index arrays are int32.
@@ -70,7 +70,7 @@ extern "C" {
 
 /* operator kinds */
 #define MFIPM_OP_DENSE 0 /* explicit m x n row-major matrix                                     */
-#define MFIPM_OP_PDCT 1  /* rows of the orthonormal DCT-II of length n (Section 3, eq.
+#define MFIPM_OP_PDCT 1  /* rows of the orthonormal DCT-II of length n (Section 2, eq.
                             (eq:orthonormality): A A^T = I); n a power of two, 64 <= n <= 2^20 */
 
 typedef struct mfipm_handle mfipm_handle;
@@ -89,13 +89,13 @@ typedef struct {
 } mfipm_operator;
 
 /* Parameters.  Defaults (mfipm_params_default) are the paper's values:
- * sigma1..3 = 0.1/0.5/0.8 and alpha_bar/alpha_tilde = 0.5/0.1 (Section 7.1,
- * after the algorithm), maxiters = 100 and mxiterpcg = 200 (Section 7.4),
+ * sigma1..3 = 0.1/0.5/0.8 and alpha_bar/alpha_tilde = 0.5/0.1 (Section 5.1,
+ * after the algorithm), maxiters = 100 and mxiterpcg = 200 (Section 5.4),
  * tol = 1e-8 and tolpcg = 1e-2 (inside the noisy-problem ranges of
- * Section 7.4).  eta, rho, z0, s0 are readings where the paper is silent:
+ * Section 5.4).  eta, rho, z0, s0 are readings where the paper is silent:
  * step = min(1, eta * largest feasible step); rho <= 0 selects
  * ||A||_F^2 / n, the closest scalar multiple of the identity to A^T A in the
- * Frobenius norm (Section 5, before eq. (eq:ne2_P)); z0 = s0 = 1.            */
+ * Frobenius norm (Section 4, before eq. (eq:ne2_P)); z0 = s0 = 1.            */
 typedef struct {
   double tol;         /* relative duality gap target                              */
   int32_t maxiters;   /* IPM iteration cap                                        */
@@ -117,7 +117,7 @@ typedef struct {
   int32_t ipm_iters;   /* Newton directions taken (a corrector does not count)      */
   int32_t pcg_iters;   /* operator applies inside PCG, summed over the solve        */
   int32_t correctors;  /* corrector directions computed                             */
-  int64_t nmat;        /* products with A or A^T (Section 7, symbol table: nMat)    */
+  int64_t nmat;        /* products with A or A^T (Section 5, symbol table: nMat)    */
   double rel_gap;      /* final relative duality gap                                */
   double mu;           /* final z^T s / (2n)                                         */
   double primal_obj;   /* tau 1^T z + 1/2 ||A(u-v) - b||^2                          */
@@ -163,6 +163,12 @@ int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, doub
  * operator: for PDCT the single rows array of length m_off[1]-m_off[0]; for
  * DENSE the single matrix at A_packed.  tau: HOST array of batch values.
  * state_packed may be NULL.  infos: HOST array of batch reports.
+ * DENSE with shared_op and batch >= 8 (and no team size set through
+ * mfipm_set_launch) runs all instances in lock step instead: every round
+ * applies the operator to all of them at once as two FP64 matrix-matrix
+ * products on the matrix cores (A D and A^T Y), and each instance's IPM
+ * advances on one workgroup between rounds; per instance the iterates are
+ * those of the single-instance method.
  * Errors as mfipm_solve, per instance.                                       */
 int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
                         const int64_t* a_off, int32_t op_kind, const double* A_packed,

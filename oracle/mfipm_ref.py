@@ -10,26 +10,26 @@ interior point method for compressed sensing problems"):
 
   BPDN   min_x  tau*||x||_1 + 1/2 ||A x - b||^2               (Section 1, eq.
          (formulationsnoisy1); the 1/2 follows the smooth QP below)
-  split  x = u - v, u, v >= 0, z = [u; v]                     (Section 2, eqs.
+  split  x = u - v, u, v >= 0, z = [u; v]                     (Section 1, eqs.
          (uvDef), (lintechni))
   primal min_z tau 1^T z + 1/2 ||F^T z - b||^2,  z >= 0,      (eq. (wrightBPDN))
          F^T = [A, -A]
   dual   max -1/2 z^T F F^T z  s.t. c + F F^T z - s = 0, z,s >= 0,
-         c = [tau - A^T b; tau + A^T b]                       (Section 4, eq.
+         c = [tau - A^T b; tau + A^T b]                       (Section 3, eq.
          (dualquadraticBPDN))
   Newton residuals f_z = s - c - F F^T z, f_s = sigma mu e - Z S e,
          mu = z^T s / (2n)                                    (eq. (fzfs))
   reduced system (Theta^{-1} + F F^T) dz = f_z + Z^{-1} f_s,
          ds = Z^{-1} f_s - Theta^{-1} dz, Theta = S^{-1} Z     (eq. (redNewton))
   PCG preconditioner P = [[Theta_u^{-1} + rho I, -rho I],
-                          [-rho I, Theta_v^{-1} + rho I]]     (Section 5, eq.
+                          [-rho I, Theta_v^{-1} + rho I]]     (Section 4, eq.
          (eq:ne2_P)), rho = Frobenius-closest scalar to A^T A
-  IPM loop: single-corrector primal-dual method, Section 7.1 algorithm,
-         with the parameter values listed after it and in Section 7.4.
+  IPM loop: single-corrector primal-dual method, Section 5.1 algorithm,
+         with the parameter values listed after it and in Section 5.4.
 
-Only products with A and A^T are used inside the method (Section 4: only
+Only products with A and A^T are used inside the method (Section 3: only
 matrix-vector products with F are allowed).  The function `dense_newton_matrix`
-builds H explicitly for the direct-solver variant (Section 7.6) and for tests.
+builds H explicitly for the direct-solver variant (Section 5.7) and for tests.
 
 Readings where the paper is silent (each is a parameter or documented rule):
   * 1/2 on the least-squares term (as in (wrightBPDN) and the vector c);
@@ -63,8 +63,8 @@ STATUS_NAMES = {0: "CONVERGED", 1: "MAXITER", 2: "PCG_BREAKDOWN", 3: "NONFINITE"
 @dataclass
 class Params:
     """Solver parameters.  Paper values: sigma1..3 and the two step thresholds
-    (Section 7.1, after the algorithm); maxiters and mxiterpcg (Section 7.4);
-    tol and tolpcg inside the ranges Section 7.4 gives for noisy problems."""
+    (Section 5.1, after the algorithm); maxiters and mxiterpcg (Section 5.4);
+    tol and tolpcg inside the ranges Section 5.4 gives for noisy problems."""
     tol: float = 1e-8
     maxiters: int = 100
     tolpcg: float = 1e-2
@@ -81,6 +81,7 @@ class Params:
     tolpcg_adj: float = 1e-12
     mxiterpcg_adj: int = 1000
     step_min: float = 1e-14   # both step sizes below this -> STEP_UNDERFLOW
+    reduced: int = 0          # 1: PCG on the n x n system of the Theorem (see pcg_reduced)
 
 
 # --- operators ----------------------------------------------------------------
@@ -195,7 +196,7 @@ class PCGResult:
 
 def pcg(op, theta_inv, rho, rhs, tol, maxit) -> PCGResult:
     """Preconditioned conjugate gradients on (eq:ne2_matrix) with P of
-    (eq:ne2_P) (Section 5).  x0 = 0; the test ||r|| <= tol ||rhs|| (squared
+    (eq:ne2_P) (Section 4).  x0 = 0; the test ||r|| <= tol ||rhs|| (squared
     form) precedes every operator apply; `iters` counts operator applies."""
     x = np.zeros_like(rhs)
     r = rhs.copy()
@@ -234,8 +235,78 @@ def pcg(op, theta_inv, rho, rhs, tol, maxit) -> PCGResult:
     return PCGResult(x=x, iters=it, status=status, hit_cap=hit_cap, rel_res=rel)
 
 
+def reduced_system(theta_inv, rhs):
+    """The n x n system behind the Theorem (thm:ne2_prec) of Section 4.
+    Writing the two block rows of (eq:ne2_H) with d = du - dv,
+        Theta_u^{-1} du + A^T A d = r_u,    Theta_v^{-1} dv - A^T A d = r_v,
+    and eliminating du = Theta_u (r_u - A^T A d), dv = Theta_v (r_v + A^T A d)
+    gives (Theta_bar^{-1} + A^T A) d = Theta_bar^{-1} (Theta_u r_u - Theta_v r_v)
+    with Theta_bar = Theta_u + Theta_v.  Returns (Theta_bar^{-1}, right-hand
+    side), both written with Theta^{-1} entries only:
+    Theta_bar^{-1} = tu tv / (tu + tv), rhs = (tv r_u - tu r_v) / (tu + tv)."""
+    n = rhs.shape[0] // 2
+    tu, tv = theta_inv[:n], theta_inv[n:]
+    ru, rv = rhs[:n], rhs[n:]
+    return tu * tv / (tu + tv), (tv * ru - tu * rv) / (tu + tv)
+
+
+def back_substitute(theta_inv, rhs, d):
+    """The 2n direction from d = du - dv: adding the two block rows gives
+    Theta_u^{-1} du + Theta_v^{-1} dv = r_u + r_v, so
+    du = (r_u + r_v + tv d) / (tu + tv) and dv = du - d (no operator product)."""
+    n = rhs.shape[0] // 2
+    tu, tv = theta_inv[:n], theta_inv[n:]
+    du = (rhs[:n] + rhs[n:] + tv * d) / (tu + tv)
+    return np.concatenate([du, du - d])
+
+
+def pcg_reduced(op, theta_inv, rho, rhs, tol, maxit) -> PCGResult:
+    """PCG on the reduced system with the n x n preconditioner
+    Theta_bar^{-1} + rho I of the Theorem (the same non-unit spectrum as the
+    2n block-preconditioned system), then the back-substitution.  x0 = 0; the
+    test ||r|| <= tol ||rhs_bar|| on the reduced residual precedes every
+    operator apply; `iters` counts operator applies."""
+    tb, rb = reduced_system(theta_inv, rhs)
+    x = np.zeros_like(rb)
+    r = rb.copy()
+    rhs2 = float(rb @ rb)
+    y = r / (tb + rho)
+    p = y.copy()
+    rty = float(r @ y)
+    it = 0
+    status = 0
+    hit_cap = False
+    while True:
+        rr = float(r @ r)
+        if not math.isfinite(rr):
+            status = NONFINITE
+            break
+        if rr <= tol * tol * rhs2:
+            break
+        if it == maxit:
+            hit_cap = True
+            break
+        q = tb * p + op.rmatvec(op.matvec(p))
+        it += 1
+        pq = float(p @ q)
+        if not pq > 0.0:
+            status = NONFINITE if not math.isfinite(pq) else PCG_BREAKDOWN
+            break
+        alpha = rty / pq
+        x += alpha * p
+        r -= alpha * q
+        y = r / (tb + rho)
+        rty_new = float(r @ y)
+        beta = rty_new / rty
+        rty = rty_new
+        p = y + beta * p
+    rel = math.sqrt(float(r @ r) / rhs2) if rhs2 > 0 else 0.0
+    return PCGResult(x=back_substitute(theta_inv, rhs, x), iters=it, status=status, hit_cap=hit_cap,
+                     rel_res=rel)
+
+
 def direct_solve(op, theta_inv, rhs) -> PCGResult:
-    """Exact Newton direction by Cholesky of the explicit H (Section 7.6)."""
+    """Exact Newton direction by Cholesky of the explicit H (Section 5.7)."""
     H = dense_newton_matrix(op, theta_inv)
     c = scipy.linalg.cho_factor(H)
     return PCGResult(x=scipy.linalg.cho_solve(c, rhs), iters=0, status=0, hit_cap=False,
@@ -251,7 +322,7 @@ def max_step(v: np.ndarray, dv: np.ndarray) -> float:
 
 
 def step_length(v, dv, eta) -> float:
-    """Step in [0, 1]: min(1, eta * largest feasible step) (Section 7.1)."""
+    """Step in [0, 1]: min(1, eta * largest feasible step) (Section 5.1)."""
     return min(1.0, eta * max_step(v, dv))
 
 
@@ -295,7 +366,7 @@ class SolveResult:
 
 def solve(op, b, tau, params: Params | None = None, linsolve: str = "pcg",
           record: bool = False) -> SolveResult:
-    """Single-corrector primal-dual matrix-free IPM (Section 7.1 algorithm)."""
+    """Single-corrector primal-dual matrix-free IPM (Section 5.1 algorithm)."""
     p = params or Params()
     n = op.n
     b = np.asarray(b, dtype=np.float64)
@@ -313,6 +384,8 @@ def solve(op, b, tau, params: Params | None = None, linsolve: str = "pcg",
     def lin(theta_inv, rhs):
         if linsolve == "direct":
             return direct_solve(op, theta_inv, rhs)
+        if p.reduced:
+            return pcg_reduced(op, theta_inv, rho, rhs, p.tolpcg, p.mxiterpcg)
         return pcg(op, theta_inv, rho, rhs, p.tolpcg, p.mxiterpcg)
 
     while True:
@@ -404,7 +477,8 @@ def backward(op, z, s, grad_x, params: Params | None = None, rho: float | None =
     c + F F^T z - s = 0 and Z S e = mu e (mu fixed) gives
     (Theta^{-1} + F F^T) dz = F db - 1 dtau.  With H w = [g_x; -g_x]:
     dL/db = A (w_u - w_v),  dL/dtau = -1^T w.
-    `method` is "pcg" (the same PCG, tight tolerance) or "dense" (Cholesky)."""
+    `method` is "pcg" (the same PCG as the forward solve, 2n or reduced per
+    params.reduced, at the adjoint tolerance) or "dense" (Cholesky)."""
     p = params or Params()
     n = op.n
     if rho is None:
@@ -413,6 +487,8 @@ def backward(op, z, s, grad_x, params: Params | None = None, rho: float | None =
     rhs = np.concatenate([grad_x, -grad_x])
     if method == "dense":
         res = direct_solve(op, theta_inv, rhs)
+    elif p.reduced:
+        res = pcg_reduced(op, theta_inv, rho, rhs, p.tolpcg_adj, p.mxiterpcg_adj)
     else:
         res = pcg(op, theta_inv, rho, rhs, p.tolpcg_adj, p.mxiterpcg_adj)
     w = res.x
@@ -427,7 +503,7 @@ def soft_threshold(v, t):
 
 
 def support_from_state(z, s, n):
-    """Index set B of the paper (Section 5, eq. (eq:thetas_split)):
+    """Index set B of the paper (Section 4, eq. (eq:thetas_split)):
     Theta_j = z_j / s_j >> 1.  Returns (support indices, signs)."""
     th = z / s
     tu, tv = th[:n], th[n:]

@@ -1,8 +1,8 @@
 // Device-side driver of the single-corrector primal-dual matrix-free IPM
-// (Section 7.1 algorithm) and of its PCG inner solver (Section 5), written
+// (Section 5.1 algorithm) and of its PCG inner solver (Section 4), written
 // once over an operator policy (OpDense / OpPdct).  Per-index data are
 // interleaved (u_i, v_i) pairs (double2) so that the 2x2 block structure of
-// H and P (Section 5, eqs. (eq:ne2_H), (eq:ne2_P)) is local to one index.
+// H and P (Section 4, eqs. (eq:ne2_H), (eq:ne2_P)) is local to one index.
 //
 // Every pass distributes its items over the workgroups of a team; every
 // reduction is first done per item (fixed order inside the workgroup), then
@@ -716,7 +716,7 @@ __device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, con
   return 0;
 }
 
-// rho: Frobenius-closest scalar to A^T A (Section 5, before eq. (eq:ne2_P)).
+// rho: Frobenius-closest scalar to A^T A (Section 4, before eq. (eq:ne2_P)).
 __device__ __forceinline__ double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
   const int ni = op.nF();
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
@@ -736,7 +736,7 @@ __device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& a
 
 // ------------------------------------------------------------------------
 // PCG on (Theta^{-1} + F F^T) x = rhs with the block preconditioner
-// (Section 5), two team barriers per iteration.  On entry R = rhs, X = 0,
+// (Section 4), two team barriers per iteration.  On entry R = rhs, X = 0,
 // TI set, and the operator holds the first gather d(y0) (y0 = P^{-1} rhs)
 // from the pass that built rhs; rhs2 = ||rhs||^2, gamma = rhs^T y0,
 // yty = y0^T Theta^{-1} y0.  Per iteration:

@@ -18,6 +18,7 @@
 
 #include "../../include/mfipm.h"
 #include "ipm.h"
+#include "lockstep.h"
 
 static_assert(sizeof(DevParams) == sizeof(mfipm_params), "params mirror");
 static_assert(sizeof(DevInfo) == sizeof(mfipm_info), "info mirror");
@@ -69,6 +70,7 @@ struct mfipm_handle {
   hipEvent_t ev0, ev1;
   double last_ms;
   int occ[2][2];             // [op][bwd] max resident workgroups per CU
+  int occ_ls;                // the same for the lock-step kernel
   size_t scratch_lane[2][2];  // [op][bwd] private bytes per lane
   // twiddle tables (device, owned by the handle), one per table resolution
   cplx* tw[32];
@@ -464,6 +466,125 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   return rc;
 }
 
+// ---- lock-step path: many signals sharing one dense A ----
+// Batches of at least this many signals on one shared dense matrix take the
+// lock-step path (unless a team size is requested).
+constexpr int kLockstepMinBatch = 8;
+
+struct LsLayout {
+  size_t ctl, info, inst, st, mode, V, D, Y, Yp, T, part, total;
+};
+
+LsLayout ls_layout(long long n, long long m, int B) {
+  LsLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t& field, size_t bytes) {
+    field = off;
+    off += align_up(bytes);
+  };
+  take(L.ctl, 256 + MF_CTL_BYTES);
+  take(L.info, (size_t)B * sizeof(DevInfo));
+  take(L.inst, (size_t)B * sizeof(InstDesc));
+  take(L.st, (size_t)B * sizeof(SigState));
+  take(L.mode, (size_t)B * sizeof(int));
+  take(L.V, (size_t)B * 8 * (size_t)n * sizeof(double2));
+  take(L.D, (size_t)B * (size_t)n * sizeof(double));
+  take(L.Y, (size_t)B * (size_t)m * sizeof(double));
+  take(L.Yp, (size_t)LS_SPLIT * B * (size_t)m * sizeof(double));
+  take(L.T, (size_t)B * (size_t)n * sizeof(double));
+  take(L.part, (size_t)((m + 7) / 8 + 64) * MF_MAXK * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+bool use_lockstep(const mfipm_handle* h, int op_kind, int shared_op, int batch) {
+  return op_kind == MFIPM_OP_DENSE && shared_op && batch >= kLockstepMinBatch &&
+         batch <= LS_MAX_GROUPS * LS_TN && h->req_team <= 0;
+}
+
+int launch_lockstep(mfipm_handle* h, const Problem& P, const double* A, const double* b, double* x, double* state,
+                    void* ws, size_t ws_bytes, mfipm_info* infos) {
+  int rc = validate(h, P);
+  if (rc) return rc;
+  if (!ws || !A || !b || !x) return MFIPM_ERR_INVALID_ARG;
+  if (h->occ_ls < 1) return MFIPM_ERR_HIP;
+  const int B = P.batch;
+  const long long n = P.n_max, m = P.m_max;
+  const LsLayout L = ls_layout(n, m, B);
+  if (ws_bytes < L.total) return MFIPM_ERR_WORKSPACE_TOO_SMALL;
+  const int gmax = h->occ_ls * h->num_cu;
+  const int grid = std::max(1, std::min(h->req_wg > 0 ? h->req_wg : h->num_cu, gmax));
+  char* base = (char*)ws;
+  const size_t desc_bytes = (size_t)B * sizeof(InstDesc);
+  const size_t back_bytes = align_up((size_t)B * sizeof(DevInfo)) + 256;
+  const size_t need = std::max(desc_bytes, back_bytes);
+  if (h->pinned_bytes < need) {
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+    if (hipHostMalloc((void**)&h->pinned, need, hipHostMallocDefault) != hipSuccess) return MFIPM_ERR_HIP;
+    h->pinned_bytes = need;
+  }
+  InstDesc* inst = reinterpret_cast<InstDesc*>(h->pinned);
+  for (int i = 0; i < B; ++i) {
+    inst[i].n = P.n_off[i + 1] - P.n_off[i];
+    inst[i].m = P.m_off[i + 1] - P.m_off[i];
+    inst[i].n_off = P.n_off[i];
+    inst[i].m_off = P.m_off[i];
+    inst[i].a_off = 0;
+    inst[i].tau = P.tau[i];
+  }
+  hipStream_t s = h->stream;
+  if (hipMemcpyAsync(base + L.inst, inst, desc_bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    return MFIPM_ERR_HIP;
+  }
+  auto fail = [&](int code) {
+    (void)hipStreamSynchronize(s);
+    return code;
+  };
+  if (hipMemsetAsync(base + L.ctl, 0, 256 + MF_CTL_BYTES, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
+  LArgs a{};
+  a.inst = (const InstDesc*)(base + L.inst);
+  a.B = B;
+  a.n = n;
+  a.m = m;
+  a.A = A;
+  a.b = b;
+  a.x = x;
+  a.state = state;
+  a.info = (DevInfo*)(base + L.info);
+  std::memcpy(&a.prm, &h->prm, sizeof(DevParams));
+  a.st = (SigState*)(base + L.st);
+  a.mode = (int*)(base + L.mode);
+  a.V = (double2*)(base + L.V);
+  a.D = (double*)(base + L.D);
+  a.Y = (double*)(base + L.Y);
+  a.Yp = (double*)(base + L.Yp);
+  a.T = (double*)(base + L.T);
+  a.part = (double*)(base + L.part);
+  a.abort_flag = (int*)(base + L.ctl + 64);
+  a.ctl = (unsigned long long*)(base + L.ctl + 256);
+  a.spin_ticks = (unsigned long long)h->wall_khz * 1000ull * 5ull;
+  void* args[] = {&a};
+  if (hipEventRecord(h->ev0, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_mfipm_lockstep), dim3(grid), dim3(MF_THREADS),
+                                 args, (unsigned)sizeof(GemmLDS), s) != hipSuccess)
+    return fail(MFIPM_ERR_HIP);
+  if (hipEventRecord(h->ev1, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
+  const DevInfo* dinf = reinterpret_cast<const DevInfo*>(h->pinned);
+  const int* ctl = reinterpret_cast<const int*>(h->pinned + align_up((size_t)B * sizeof(DevInfo)));
+  if (hipMemcpyAsync(h->pinned, base + L.info, sizeof(DevInfo) * B, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync((void*)ctl, base + L.ctl, 128, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(MFIPM_ERR_HIP);
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
+  for (int i = 0; i < B; ++i)
+    if (infos) std::memcpy(&infos[i], &dinf[i], sizeof(mfipm_info));
+  return ctl[16] != 0 ? MFIPM_ERR_HIP : MFIPM_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -532,6 +653,16 @@ int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
       }
       h->scratch_lane[op][bwd] = fa.localSizeBytes;
     }
+  {
+    const void* k = reinterpret_cast<const void*>(&k_mfipm_lockstep);
+    int occ = 0;
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(GemmLDS)) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, MF_THREADS, sizeof(GemmLDS)) != hipSuccess) {
+      delete h;
+      return MFIPM_ERR_HIP;
+    }
+    h->occ_ls = occ;
+  }
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
     delete h;
     return MFIPM_ERR_HIP;
@@ -577,6 +708,7 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
     const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch), tl);
     best = std::max(best, gl.total);
   }
+  if (op_kind == MFIPM_OP_DENSE && batch >= kLockstepMinBatch) best = std::max(best, ls_layout(max_n, max_m, batch).total);
   *bytes = best;
   return MFIPM_OK;
 }
@@ -601,6 +733,8 @@ int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, co
     mmax = std::max<long long>(mmax, m_off[i + 1] - m_off[i]);
   }
   Problem P{batch, op_kind, shared_op ? 1 : 0, n_off, m_off, a_off, tau, nmax, mmax};
+  if (use_lockstep(h, op_kind, shared_op, batch))
+    return launch_lockstep(h, P, A_packed, b_packed, x_packed, state_packed, ws, ws_bytes, infos);
   return launch(h, P, 0, A_packed, rows_packed, b_packed, x_packed, state_packed, nullptr, nullptr, nullptr, ws,
                 ws_bytes, infos);
 }

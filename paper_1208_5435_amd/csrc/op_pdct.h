@@ -2,8 +2,8 @@
 // m sampled rows): the product K d = A^T A d = C^T M C d (M = 0/1 mask of the
 // kept coefficients) and the residual A^T (A x - b) = C^T (M C x - b~), where
 // b~ is b scattered to the kept coefficients.  Orthonormal rows (A A^T = I)
-// are the property the paper's preconditioner relies on (Section 3,
-// eq. (eq:orthonormality); Section 5, eq. (eq:ne2_P) with rho = m/n).
+// are the property the paper's preconditioner relies on (Section 2,
+// eq. (eq:orthonormality); Section 4, eq. (eq:ne2_P) with rho = m/n).
 //
 // Transform path (radix-2 FFT staged in LDS; Makhoul's DCT-via-FFT reordering
 // and the half-length complex FFT of a real sequence):

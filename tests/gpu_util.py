@@ -4,7 +4,7 @@ The bar: ||x_gpu - x_cpu|| / ||x_cpu|| <= 1e-6 at the test's IPM tolerance
 (1e-8 unless stated), KKT residual <= 1e-6, identical status and IPM
 iteration counts within +-1.
 
-Two escalations exist, each printed on its own line and recorded in
+Three escalations exist, each printed on its own line and recorded in
 `EVENTS`:
   * x: when the GPU and oracle points differ by more than 1e-6 at the test
     tolerance, both sides are solved again at tolerance 1e-12 (PCG 1e-8) and
@@ -15,6 +15,11 @@ Two escalations exist, each printed on its own line and recorded in
     tolerance 1e-12 and the GPU must meet 1e-6 wherever the oracle does
     there; if even the oracle's tight point misses it, the GPU's tight point
     may be no worse than twice the oracle's.
+  * IPM iterations: when the counts differ by more than one, the oracle is
+    run again on b (1 + 1e-15) and b (1 - 1e-15); in ill-conditioned regimes
+    (tau ~ 1e-10, tol 1e-14) rounding-level changes of the input move its own
+    count by two or more, and the GPU's count must then lie within one of the
+    range those runs span.
 `strict=True` (the full-size workloads) allows no escalation.
 """
 from __future__ import annotations
@@ -67,6 +72,19 @@ def resolver(solver, **solve_kwargs):
     return run
 
 
+def check_iterations(op, b, tau, gpu_iters, ref, params=None, label="", strict=False):
+    """IPM iteration counts within ITER_SLACK, or within ITER_SLACK of the
+    span of the oracle's counts under rounding-level input perturbations."""
+    if abs(gpu_iters - ref.ipm_iters) <= ITER_SLACK:
+        return
+    assert not strict, (label, "strict gate", gpu_iters, ref.ipm_iters)
+    its = [ref.ipm_iters] + [R.solve(op, np.asarray(b) * (1.0 + e), tau, params).ipm_iters
+                             for e in (1e-15, -1e-15)]
+    _event(f"PARITY-ESCALATION iterations {label}: GPU {gpu_iters}, oracle {ref.ipm_iters}; oracle on "
+           f"b(1 +- 1e-15): {its[1:]}")
+    assert min(its) - ITER_SLACK <= gpu_iters <= max(its) + ITER_SLACK, (label, gpu_iters, its)
+
+
 def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label="", resolve=None,
                          strict=False, ref=None):
     """Runs the oracle on the same inputs (unless `ref` is given) and applies
@@ -76,7 +94,7 @@ def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label
     if ref is None:
         ref = R.solve(op, b, tau, params)
     assert info["status"] == ref.status, (label, info, R.STATUS_NAMES[ref.status])
-    assert abs(info["ipm_iters"] - ref.ipm_iters) <= ITER_SLACK, (label, info["ipm_iters"], ref.ipm_iters)
+    check_iterations(op, b, tau, info["ipm_iters"], ref, params, label, strict)
     xg = np.asarray(x_gpu)
     n = op.n
     tight = {}

@@ -117,7 +117,7 @@ def pin_dct_definition(n, m, seed):
 
 def pin_pcg_vs_direct(A, b, tau):
     """With PCG run to 1e-12 the IPM takes the same iterations and reaches the
-    same point as with exact (Cholesky) Newton directions (Section 7.6:
+    same point as with exact (Cholesky) Newton directions (Section 5.7:
     PCG needs as few IPM iterations as the direct solver).  Returns
     (|iteration difference|, relative x difference)."""
     op = R.DenseOperator(A)
@@ -214,3 +214,34 @@ def pin_kkt_handbuilt():
     sg4[0] = -sg4[0]
     errs.append(abs(R.kkt_residual(op, b, tau, x, S, sg4) - 2.0))
     return max(errs)
+
+
+def pin_reduced_direction(op, seed):
+    """The reduced system's exact solution, back-substituted, against the
+    exact 2n Newton direction (Cholesky of the explicit H): the elimination
+    of Section 4's block rows loses nothing.  Also the reduced PCG at a tight
+    tolerance against the same direction.  Returns the larger relative error."""
+    n = op.n
+    rng = rng_for(seed)
+    theta_inv = 10.0 ** rng.uniform(-3, 3, 2 * n)
+    rhs = rng.standard_normal(2 * n)
+    exact = np.linalg.solve(R.dense_newton_matrix(op, theta_inv), rhs)
+    tb, rb = R.reduced_system(theta_inv, rhs)
+    A = op.dense()
+    d = np.linalg.solve(np.diag(tb) + A.T @ A, rb)
+    e1 = np.linalg.norm(R.back_substitute(theta_inv, rhs, d) - exact) / np.linalg.norm(exact)
+    res = R.pcg_reduced(op, theta_inv, op.frob2() / n, rhs, 1e-13, 50 * n)
+    e2 = np.linalg.norm(res.x - exact) / np.linalg.norm(exact)
+    return max(e1, e2)
+
+
+def pin_reduced_vs_direct(A, b, tau):
+    """The IPM with reduced-system PCG at tolpcg 1e-12 takes the iterations of
+    the exact-Newton IPM and reaches its point (Section 5.7 comparison, with
+    the reduced system).  Returns (|iteration difference|, relative x
+    difference)."""
+    op = R.DenseOperator(A)
+    p_it = R.Params(tolpcg=1e-12, mxiterpcg=10 * A.shape[1], reduced=1)
+    r1 = R.solve(op, b, tau, p_it)
+    r2 = R.solve(op, b, tau, p_it, linsolve="direct")
+    return abs(r1.ipm_iters - r2.ipm_iters), float(np.linalg.norm(r1.x - r2.x) / np.linalg.norm(r2.x))

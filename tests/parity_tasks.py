@@ -63,3 +63,13 @@ def grad_signal(j, n, batch, x, state, info, grad_b, grad_tau, binfo):
     et_cf = abs(grad_tau - gt_cf) / abs(gt_cf)
     assert eb_cf <= 1e-5 and et_cf <= 1e-5, (j, eb_cf, et_cf)
     return j, eb, et, eb_cf, et_cf, len(S)
+
+
+def shared_dense_signal(j, x, state, info, batch):
+    """Signal j of the shared-dense batch (A drawn again from its seed):
+    oracle solve and the strict bar."""
+    inst = W.config_shared_dense(batch=batch, signals=[j])
+    op = R.DenseOperator(inst.A)
+    ref = U.check_against_oracle(op, inst.b[0], inst.tau[0], x, info, state, label=f"shared_dense[{j}]",
+                                 strict=True)
+    return j, ref.ipm_iters, info["ipm_iters"], U.rel(x, ref.x)

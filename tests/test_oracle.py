@@ -27,7 +27,7 @@ def test_paper_parameters_are_defaults():
 
 
 def test_worked_constant_C():
-    """Section 5: for |tau_hat| <= 17/20 with rho = 1/4 the separator constant is
+    """Section 4: for |tau_hat| <= 17/20 with rho = 1/4 the separator constant is
     C = 20 (0.75 + delta + 2 sqrt(1+delta))^2 / 3; the paper prints ~139.74 for
     delta <= 1 and ~50.41 for delta = 0."""
     with open(os.path.join(GOLDEN, "paper_params.json")) as f:
@@ -121,7 +121,7 @@ def test_dct_definition(n, m):
 
 @pytest.mark.parametrize("n", [32, 64, 128])
 def test_pcg_matches_direct_newton(n):
-    """Section 7.6 setup: Gaussian A, m = n/4, k = ceil(m/20), tau = 1e-3,
+    """Section 5.7 setup: Gaussian A, m = n/4, k = ceil(m/20), tau = 1e-3,
     noiseless."""
     m = n // 4
     k = math.ceil(m / 20)
@@ -226,3 +226,36 @@ def test_rho_is_frobenius_closest(kind):
 
 def test_kkt_residual_handbuilt():
     assert PIN.pin_kkt_handbuilt() <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["dense", "dct"])
+def test_reduced_direction_is_the_newton_direction(kind):
+    rng = PIN.rng_for(51)
+    n = 40
+    if kind == "dense":
+        op = R.DenseOperator(rng.standard_normal((12, n)) / math.sqrt(12))
+    else:
+        op = R.PartialDCTOperator(n, np.sort(rng.choice(n, 12, replace=False)))
+    assert PIN.pin_reduced_direction(op, seed=5) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_reduced_pcg_matches_direct_newton(n):
+    m = n // 4
+    rng = PIN.rng_for(n + 1)
+    A = rng.standard_normal((m, n)) / math.sqrt(m)
+    x = np.zeros(n)
+    x[rng.choice(n, 2, replace=False)] = rng.choice([-1.0, 1.0], 2)
+    dit, dx = PIN.pin_reduced_vs_direct(A, A @ x, 1e-3)
+    assert dit == 0
+    assert dx <= 1e-8
+
+
+def test_reduced_adjoint_matches_dense():
+    A, b, tau, xt = PIN.dense_problem(40, 120, 4, seed=57)
+    op = R.DenseOperator(A)
+    res = R.solve(op, b, tau, R.Params(reduced=1))
+    g1 = R.backward(op, res.z, res.s, res.x - xt, R.Params(reduced=1))
+    g2 = R.backward(op, res.z, res.s, res.x - xt, method="dense")
+    assert np.linalg.norm(g1.grad_b - g2.grad_b) <= 1e-8 * np.linalg.norm(g2.grad_b)
+    assert abs(g1.grad_tau - g2.grad_tau) <= 1e-8 * abs(g2.grad_tau)

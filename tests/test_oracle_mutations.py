@@ -192,3 +192,24 @@ def _kkt_zero(op, b, tau, x, support=None, signs=None):
 def test_kkt_residual_slip_caught(monkeypatch, bad):
     monkeypatch.setattr(R, "kkt_residual", bad)
     assert PIN.pin_kkt_handbuilt() > 1e-3
+
+
+def test_back_substitution_slip_caught(monkeypatch):
+    """du = (r_u + r_v + tu d) / (tu + tv): the wrong diagonal."""
+    def bad(theta_inv, rhs, d):
+        n = rhs.shape[0] // 2
+        tu, tv = theta_inv[:n], theta_inv[n:]
+        du = (rhs[:n] + rhs[n:] + tu * d) / (tu + tv)
+        return np.concatenate([du, du - d])
+    monkeypatch.setattr(R, "back_substitute", bad)
+    assert PIN.pin_reduced_direction(_small_ops()[0], seed=5) > 1e-3
+
+
+def test_reduced_rhs_slip_caught(monkeypatch):
+    """The reduced right-hand side with a sign slip."""
+    def bad(theta_inv, rhs):
+        n = rhs.shape[0] // 2
+        tu, tv = theta_inv[:n], theta_inv[n:]
+        return tu * tv / (tu + tv), (tv * rhs[:n] + tu * rhs[n:]) / (tu + tv)
+    monkeypatch.setattr(R, "reduced_system", bad)
+    assert PIN.pin_reduced_direction(_small_ops()[1], seed=5) > 1e-3

@@ -14,8 +14,8 @@ Operators:
   * dense: A with i.i.d. N(0, 1/m) entries, row-major (C order), m x n;
   * partial DCT: A = R_m C, where C is the orthonormal DCT-II of length n and
     R_m keeps m distinct rows drawn uniformly without replacement, sorted
-    ascending (paper, Section 3 orthonormal rows, eq. (eq:orthonormality), and
-    Section 6 phase-transition setup "normalized DCT").
+    ascending (paper, Section 2 orthonormal rows, eq. (eq:orthonormality), and
+    Section 5.8 phase-transition setup "normalized DCT").
 
 Draw order inside one instance is fixed: operator (A or rows) -> support ->
 amplitudes / signs -> noise.  Every generator is numpy's PCG64 with the stated
