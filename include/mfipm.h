@@ -55,6 +55,11 @@ extern "C" {
 #define MFIPM_ERR_WORKSPACE_TOO_SMALL (-3)
 #define MFIPM_ERR_NO_STATE (-4)
 #define MFIPM_ERR_DEVICE_CHECK (-5) /* device-side input check failed (e.g. rows not sorted/distinct) */
+#define MFIPM_ERR_TOO_LARGE (-6)    /* mfipm_solve_noalloc: the call's workspace exceeds the static
+                                       scratch (MFIPM_NOALLOC_SCRATCH_BYTES)                      */
+
+/* Bytes of the static per-device scratch used by mfipm_solve_noalloc. */
+#define MFIPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
 /* solver outcome (mfipm_info.status) */
 #define MFIPM_STATUS_CONVERGED 0      /* relative duality gap <= tol                        */
@@ -155,6 +160,26 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
  * DEVICE_CHECK (rows not sorted/distinct/in range); HIP.                     */
 int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau,
                 double* x, double* state, void* ws, size_t ws_bytes, mfipm_info* info);
+
+/* For callers that cannot allocate memory (code under stream/graph capture,
+ * tight serving loops, harnesses that forbid allocation): mfipm_solve
+ * without a workspace argument.  The workspace is a static device array of
+ * MFIPM_NOALLOC_SCRATCH_BYTES (64 MiB) that every device holds from the
+ * first mfipm_create on it until the process ends; the FFT roots of unity
+ * come from a static full-resolution table filled at that mfipm_create.  The
+ * call allocates nothing (no hipMalloc, hipHostMalloc or hipFree; report
+ * transfers go through the host stack) and clears the control words it needs
+ * with a kernel.  It must be called with the handle's device current.
+ * Arguments, layouts, results and errors as mfipm_solve, plus TOO_LARGE when
+ * mfipm_workspace_size(h, op->op, op->n, op->m, 1) exceeds the scratch
+ * (e.g. partial DCT n >= 2^18), and HIP when the static memory could not be
+ * set up.  All calls on one device share the array and keep no state in it
+ * between calls: calls from several host threads on one device are
+ * serialised by the library; calls from several processes each use their
+ * own copy.  Results may differ from mfipm_solve in the last bits (partial
+ * DCT: the twiddles come from the full-resolution table).                    */
+int mfipm_solve_noalloc(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau,
+                        double* x, double* state, mfipm_info* info);
 
 /* Solves `batch` independent instances in one persistent launch; teams of
  * workgroups take instances from a device queue in the host-given order

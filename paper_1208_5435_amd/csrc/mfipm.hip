@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -57,6 +58,27 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
   }
 }
 
+// Clears `words` 64-bit words (control words of a call on the static
+// scratch; a kernel rather than a memset node, so a captured call replays it).
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long* p, long words) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (long)gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------------
+// Static device memory of the no-allocation entry point (mfipm_solve_noalloc).
+// `scratch` replaces the caller's workspace; `tw_full` holds the roots of
+// unity at the largest supported resolution (2^22 = 4 x 2^20: 2^11 low and
+// 2^11 high entries), which serve every transform length through the
+// resolution shift.  Each device that loads the library holds both until the
+// process ends.  In host code these names are host-side stand-ins: only the
+// per-device addresses from hipGetSymbolAddress may reach a kernel or a copy.
+// ------------------------------------------------------------------------
+#define MFIPM_NOALLOC_TW_LOG2 22
+#define MFIPM_NOALLOC_TW_LO_BITS 11
+static __device__ __align__(256) char scratch[MFIPM_NOALLOC_SCRATCH_BYTES];
+static __device__ __align__(256) cplx tw_full[(1 << MFIPM_NOALLOC_TW_LO_BITS) +
+                                              (1 << (MFIPM_NOALLOC_TW_LOG2 - MFIPM_NOALLOC_TW_LO_BITS))];
+
 // ------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------
@@ -77,6 +99,10 @@ struct mfipm_handle {
   // pinned host staging for the per-call uploads and read-backs
   char* pinned;
   size_t pinned_bytes;
+  // this device's static scratch and full twiddle table (device addresses),
+  // or null when their set-up failed
+  char* na_scratch;
+  const cplx* na_tw;
 };
 
 // Upper bound on private (scratch) memory of one dispatch: all workgroups of a
@@ -315,15 +341,63 @@ int validate(const mfipm_handle* h, const Problem& P) {
   return MFIPM_OK;
 }
 
+// Device addresses of the static scratch and twiddle table, looked up once
+// per device (with that device current) and kept for the process.  The
+// table is filled at the same time.
+constexpr int kMaxDevices = 64;
+struct NoallocDevice {
+  std::once_flag once;
+  int rc = MFIPM_ERR_HIP;
+  char* scratch = nullptr;
+  cplx* tw = nullptr;
+  std::mutex call;  // no-allocation calls on one device run one at a time
+};
+NoallocDevice g_noalloc[kMaxDevices];
+
+int noalloc_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return MFIPM_ERR_HIP;
+  NoallocDevice& d = g_noalloc[dev];
+  std::call_once(d.once, [&d] {
+    void* sp = nullptr;
+    void* tp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return;
+    if (hipGetSymbolAddress(&tp, HIP_SYMBOL(tw_full)) != hipSuccess || !tp) return;
+    std::vector<cplx> lo, hi;
+    fill_twiddles(lo, hi, MFIPM_NOALLOC_TW_LOG2, MFIPM_NOALLOC_TW_LO_BITS);
+    cplx* t = static_cast<cplx*>(tp);
+    if (hipMemcpy(t, lo.data(), lo.size() * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t + lo.size(), hi.data(), hi.size() * sizeof(cplx), hipMemcpyHostToDevice) != hipSuccess)
+      return;
+    d.scratch = static_cast<char*>(sp);
+    d.tw = t;
+    d.rc = MFIPM_OK;
+  });
+  return d.rc;
+}
+
 #define HIP_TRY(expr)                      \
   do {                                     \
     if ((expr) != hipSuccess) return MFIPM_ERR_HIP; \
   } while (0)
 
+// Where a call's device workspace and host transfers live.  Ordinary calls:
+// the caller's workspace, the handle's pinned staging and the handle's
+// twiddle tables.  No-allocation calls (tw_fixed set): the device's static
+// scratch, a staging buffer on the host stack and the static full-resolution
+// twiddle table -- nothing is allocated anywhere in the call.
+struct Backing {
+  char* ws;
+  size_t ws_bytes;
+  const cplx* tw_fixed;
+};
+
 // Shared launch path of solve (bwd = 0) and backward (bwd = 1).
 int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const int32_t* rows, const double* b,
-           double* x, double* state, const double* grad_x, double* grad_b, double* grad_tau, void* ws,
-           size_t ws_bytes, mfipm_info* infos) {
+           double* x, double* state, const double* grad_x, double* grad_b, double* grad_tau,
+           const Backing& bk, mfipm_info* infos) {
+  void* ws = bk.ws;
+  const size_t ws_bytes = bk.ws_bytes;
+  const bool noalloc = bk.tw_fixed != nullptr;
   int rc = validate(h, P);
   if (rc) return rc;
   if (!ws) return MFIPM_ERR_INVALID_ARG;
@@ -357,26 +431,42 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     return MFIPM_ERR_HIP;
 
   const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max));
-  const GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
-  if (ws_bytes < gl.total) return MFIPM_ERR_WORKSPACE_TOO_SMALL;
+  GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
+  if (ws_bytes < gl.total) return noalloc ? MFIPM_ERR_TOO_LARGE : MFIPM_ERR_WORKSPACE_TOO_SMALL;
+  int tw_log2n_max = ilog2_host(P.n_max);
+  if (noalloc && P.op_kind == MFIPM_OP_PDCT) {
+    gl.lo_bits = MFIPM_NOALLOC_TW_LO_BITS;
+    gl.hi_count = 1LL << (MFIPM_NOALLOC_TW_LOG2 - MFIPM_NOALLOC_TW_LO_BITS);
+    tw_log2n_max = MFIPM_NOALLOC_TW_LOG2 - 2;
+  }
 
   char* base = (char*)ws;
-  // Pinned staging (the previous call has synchronised): descriptors and the
-  // launch order go up in one copy; reports and the abort flag come back into
-  // the same buffer.
+  // Staging (the previous call has synchronised): descriptors and the launch
+  // order go up in one copy; reports and the abort flag come back into the
+  // same buffer.  Pinned and owned by the handle, or on the stack for the
+  // no-allocation entry point (single instance).
   const size_t desc_bytes = (size_t)P.batch * (sizeof(InstDesc) + sizeof(int));
   const size_t back_bytes = align_up((size_t)P.batch * sizeof(DevInfo)) + 256;
   const size_t need = std::max(desc_bytes, back_bytes);
-  if (h->pinned_bytes < need) {
-    if (h->pinned) (void)hipHostFree(h->pinned);
-    h->pinned = nullptr;
-    h->pinned_bytes = 0;
-    if (hipHostMalloc((void**)&h->pinned, need, hipHostMallocDefault) != hipSuccess) return MFIPM_ERR_HIP;
-    h->pinned_bytes = need;
+  alignas(256) char stack_stage[1024];
+  char* stage = stack_stage;
+  if (noalloc) {
+    if (need > sizeof(stack_stage)) return MFIPM_ERR_INVALID_ARG;
+  } else {
+    if (h->pinned_bytes < need) {
+      if (h->pinned) (void)hipHostFree(h->pinned);
+      h->pinned = nullptr;
+      h->pinned_bytes = 0;
+      if (hipHostMalloc((void**)&h->pinned, need, hipHostMallocDefault) != hipSuccess) return MFIPM_ERR_HIP;
+      h->pinned_bytes = need;
+    }
+    stage = h->pinned;
   }
-  char* desc = h->pinned;
+  char* desc = stage;
   InstDesc* inst = reinterpret_cast<InstDesc*>(desc);
-  std::vector<int> order(P.batch);
+  // launch order: largest instance first, ties by index (the staging buffer
+  // holds it after the descriptors; std::sort needs no extra memory)
+  int* order = reinterpret_cast<int*>(desc + (size_t)P.batch * sizeof(InstDesc));
   for (int i = 0; i < P.batch; ++i) {
     inst[i].n = P.n_off[i + 1] - P.n_off[i];
     inst[i].m = P.m_off[i + 1] - P.m_off[i];
@@ -384,15 +474,14 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     inst[i].m_off = P.m_off[i];
     inst[i].a_off = (P.op_kind == MFIPM_OP_DENSE && !P.shared_op) ? P.a_off[i] : 0;
     inst[i].tau = P.tau ? P.tau[i] : 0.0;
+    order[i] = i;
   }
-  for (int i = 0; i < P.batch; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+  std::sort(order, order + P.batch, [&](int u, int v) {
     const double cu = (double)inst[u].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[u].m : 1);
     const double cv = (double)inst[v].n * (double)(P.op_kind == MFIPM_OP_DENSE ? inst[v].m : 1);
-    return cu > cv;
+    return cu > cv || (cu == cv && u < v);
   });
   hipStream_t s = h->stream;
-  std::memcpy(desc + (size_t)P.batch * sizeof(InstDesc), order.data(), sizeof(int) * P.batch);
   if (hipMemcpyAsync(base + gl.inst, desc, desc_bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
     (void)hipStreamSynchronize(s);
     return MFIPM_ERR_HIP;
@@ -403,15 +492,21 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     (void)hipStreamSynchronize(s);
     return code;
   };
-  const int logn_max = ilog2_host(P.n_max);
   const cplx* tw = nullptr;
   if (P.op_kind == MFIPM_OP_PDCT) {
-    tw = twiddle_tables(h, logn_max + 2, gl.lo_bits);
+    tw = noalloc ? bk.tw_fixed : twiddle_tables(h, tw_log2n_max + 2, gl.lo_bits);
     if (!tw) return fail(MFIPM_ERR_HIP);
   }
   // zero the control words: queue head, abort flag, team barriers and slots
-  if (hipMemsetAsync(base + gl.ctl, 0, 256 + (size_t)num_teams * MF_CTL_BYTES, s) != hipSuccess)
+  const size_t ctl_bytes = 256 + (size_t)num_teams * MF_CTL_BYTES;
+  if (noalloc) {
+    const long words = (long)(ctl_bytes / sizeof(unsigned long long));
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<long>(64, (words + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(base + gl.ctl), words);
+    if (hipGetLastError() != hipSuccess) return fail(MFIPM_ERR_HIP);
+  } else if (hipMemsetAsync(base + gl.ctl, 0, ctl_bytes, s) != hipSuccess) {
     return fail(MFIPM_ERR_HIP);
+  }
 
   KArgs a{};
   a.inst = (const InstDesc*)(base + gl.inst);
@@ -436,7 +531,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   a.tw_lo = tw;
   a.tw_hi = tw ? tw + ((size_t)1 << gl.lo_bits) : nullptr;
   a.tw_lo_bits = gl.lo_bits;
-  a.tw_log2n_max = logn_max;
+  a.tw_log2n_max = tw_log2n_max;
   a.team_size = team_size;
   a.tile_param = h->req_tile;
   a.spin_ticks = (unsigned long long)h->wall_khz * 1000ull * 5ull;  // 5 s per wait
@@ -448,9 +543,9 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
                                  (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
     return fail(MFIPM_ERR_HIP);
   if (hipEventRecord(h->ev1, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
-  const DevInfo* dinf = reinterpret_cast<const DevInfo*>(h->pinned);
-  const int* ctl = reinterpret_cast<const int*>(h->pinned + align_up((size_t)P.batch * sizeof(DevInfo)));
-  if (hipMemcpyAsync(h->pinned, base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s) !=
+  const DevInfo* dinf = reinterpret_cast<const DevInfo*>(stage);
+  const int* ctl = reinterpret_cast<const int*>(stage + align_up((size_t)P.batch * sizeof(DevInfo)));
+  if (hipMemcpyAsync(stage, base + gl.info, sizeof(DevInfo) * P.batch, hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
       hipMemcpyAsync((void*)ctl, base + gl.ctl, 128, hipMemcpyDeviceToHost, s) != hipSuccess)
     return fail(MFIPM_ERR_HIP);
@@ -667,6 +762,12 @@ int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
     delete h;
     return MFIPM_ERR_HIP;
   }
+  // the no-allocation entry point's static memory on this device (once per
+  // device; a failure only disables that entry point)
+  if (noalloc_setup(h->device) == MFIPM_OK) {
+    h->na_scratch = g_noalloc[h->device].scratch;
+    h->na_tw = g_noalloc[h->device].tw;
+  }
   *hp = h;
   return MFIPM_OK;
 }
@@ -719,7 +820,22 @@ int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, doub
   if (op->op == MFIPM_OP_DENSE && op->lda != op->n) return MFIPM_ERR_INVALID_ARG;
   const int64_t n_off[2] = {0, op->n}, m_off[2] = {0, op->m}, a_off[2] = {0, op->m * op->n};
   Problem P{1, op->op, 1, n_off, m_off, a_off, &tau, op->n, op->m};
-  return launch(h, P, 0, op->A, op->rows, b, x, state, nullptr, nullptr, nullptr, ws, ws_bytes, info);
+  return launch(h, P, 0, op->A, op->rows, b, x, state, nullptr, nullptr, nullptr, Backing{(char*)ws, ws_bytes, nullptr},
+                info);
+}
+
+int mfipm_solve_noalloc(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau, double* x,
+                        double* state, mfipm_info* info) {
+  if (!h || !op) return MFIPM_ERR_INVALID_ARG;
+  if (op->op == MFIPM_OP_DENSE && op->lda != op->n) return MFIPM_ERR_INVALID_ARG;
+  if (!h->na_scratch || !h->na_tw) return MFIPM_ERR_HIP;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != h->device) return MFIPM_ERR_INVALID_ARG;
+  const int64_t n_off[2] = {0, op->n}, m_off[2] = {0, op->m}, a_off[2] = {0, op->m * op->n};
+  Problem P{1, op->op, 1, n_off, m_off, a_off, &tau, op->n, op->m};
+  std::lock_guard<std::mutex> lock(g_noalloc[h->device].call);
+  return launch(h, P, 0, op->A, op->rows, b, x, state, nullptr, nullptr, nullptr,
+                Backing{h->na_scratch, MFIPM_NOALLOC_SCRATCH_BYTES, h->na_tw}, info);
 }
 
 int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
@@ -735,8 +851,8 @@ int mfipm_solve_batched(mfipm_handle* h, int32_t batch, const int64_t* n_off, co
   Problem P{batch, op_kind, shared_op ? 1 : 0, n_off, m_off, a_off, tau, nmax, mmax};
   if (use_lockstep(h, op_kind, shared_op, batch))
     return launch_lockstep(h, P, A_packed, b_packed, x_packed, state_packed, ws, ws_bytes, infos);
-  return launch(h, P, 0, A_packed, rows_packed, b_packed, x_packed, state_packed, nullptr, nullptr, nullptr, ws,
-                ws_bytes, infos);
+  return launch(h, P, 0, A_packed, rows_packed, b_packed, x_packed, state_packed, nullptr, nullptr, nullptr,
+                Backing{(char*)ws, ws_bytes, nullptr}, infos);
 }
 
 int mfipm_backward(mfipm_handle* h, int32_t batch, const int64_t* n_off, const int64_t* m_off,
@@ -752,7 +868,7 @@ int mfipm_backward(mfipm_handle* h, int32_t batch, const int64_t* n_off, const i
   }
   Problem P{batch, op_kind, shared_op ? 1 : 0, n_off, m_off, a_off, nullptr, nmax, mmax};
   return launch(h, P, 1, A_packed, rows_packed, nullptr, nullptr, const_cast<double*>(state_packed),
-                grad_x_packed, grad_b_packed, grad_tau, ws, ws_bytes, infos);
+                grad_x_packed, grad_b_packed, grad_tau, Backing{(char*)ws, ws_bytes, nullptr}, infos);
 }
 
 const char* mfipm_status_string(int32_t code) {
@@ -762,6 +878,7 @@ const char* mfipm_status_string(int32_t code) {
     case MFIPM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case MFIPM_ERR_NO_STATE: return "no state from a forward solve";
     case MFIPM_ERR_DEVICE_CHECK: return "device-side input check failed";
+    case MFIPM_ERR_TOO_LARGE: return "problem too large for the no-allocation scratch";
     case MFIPM_STATUS_CONVERGED: return "converged";
     case MFIPM_STATUS_MAXITER: return "iteration limit";
     case MFIPM_STATUS_PCG_BREAKDOWN: return "PCG breakdown";

@@ -24,12 +24,12 @@ OP_PDCT = 1
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "PCG_BREAKDOWN", 3: "NONFINITE", 4: "STEP_UNDERFLOW",
           5: "ABORTED", 6: "INPUT_CHECK", 7: "PCG_MAXITER"}
 ERRORS = {-1: "INVALID_ARG", -2: "HIP_ERROR", -3: "WORKSPACE_TOO_SMALL", -4: "NO_STATE",
-          -5: "DEVICE_CHECK"}
+          -5: "DEVICE_CHECK", -6: "TOO_LARGE"}
 
 # every symbol declared in include/mfipm.h
 EXPORTS = ("mfipm_params_default", "mfipm_create", "mfipm_set_params", "mfipm_destroy",
-           "mfipm_workspace_size", "mfipm_solve", "mfipm_solve_batched", "mfipm_backward",
-           "mfipm_set_launch", "mfipm_last_kernel_ms", "mfipm_status_string")
+           "mfipm_workspace_size", "mfipm_solve", "mfipm_solve_noalloc", "mfipm_solve_batched",
+           "mfipm_backward", "mfipm_set_launch", "mfipm_last_kernel_ms", "mfipm_status_string")
 
 
 class Params(ctypes.Structure):
@@ -98,6 +98,7 @@ def load_library(path: str | None = None):
     lib.mfipm_destroy.argtypes = [vp]
     lib.mfipm_workspace_size.argtypes = [vp, i32, i64, i64, i32, ctypes.POINTER(sz)]
     lib.mfipm_solve.argtypes = [vp, ctypes.POINTER(Operator), vp, dbl, vp, vp, vp, sz, I]
+    lib.mfipm_solve_noalloc.argtypes = [vp, ctypes.POINTER(Operator), vp, dbl, vp, vp, I]
     lib.mfipm_solve_batched.argtypes = [vp, i32, pi64, pi64, pi64, i32, vp, vp, i32, vp, pdbl, vp, vp, vp,
                                         sz, I]
     lib.mfipm_backward.argtypes = [vp, i32, pi64, pi64, pi64, i32, vp, vp, i32, vp, vp, vp, vp, vp, sz, I]
@@ -107,8 +108,8 @@ def load_library(path: str | None = None):
     lib.mfipm_status_string.argtypes = [i32]
     lib.mfipm_status_string.restype = ctypes.c_char_p
     for name in ("mfipm_params_default", "mfipm_create", "mfipm_set_params", "mfipm_destroy",
-                 "mfipm_workspace_size", "mfipm_solve", "mfipm_solve_batched", "mfipm_backward",
-                 "mfipm_set_launch"):
+                 "mfipm_workspace_size", "mfipm_solve", "mfipm_solve_noalloc", "mfipm_solve_batched",
+                 "mfipm_backward", "mfipm_set_launch"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -254,6 +255,29 @@ class Solver:
                                   _ptr(ws), nb, ctypes.byref(info))
         _check("mfipm_solve", rc)
         return Result(x=x, state=state, infos=[info.as_dict()], kernel_ms=self.last_kernel_ms())
+
+    def solve_noalloc(self, b, tau, x, state=None, A=None, rows=None, n=None) -> dict:
+        """mfipm_solve_noalloc: like `solve`, but the library uses its static
+        per-device scratch instead of a workspace and allocates nothing; the
+        caller passes device tensors for b, x (n) and optionally state (4n).
+        Returns the report."""
+        if A is not None:
+            m, nn = A.shape
+            op = Operator(OP_DENSE, m, nn, A.data_ptr(), nn, None)
+        else:
+            op = Operator(OP_PDCT, rows.shape[0], int(n), None, 0, rows.data_ptr())
+        if b.shape[0] != op.m or x.shape[0] != op.n or (state is not None and state.shape[0] != 4 * op.n):
+            raise ValueError("b, x or state has the wrong length")
+        for t in (b, x, state, A, rows):
+            if t is not None and (t.device != self.device or not t.is_contiguous()):
+                raise ValueError("tensors must be contiguous and on the solver's device")
+        self._apply_shape(op.op, int(op.n), int(op.m), 1, True)
+        info = Info()
+        with self.torch.cuda.device(self.device):
+            rc = self.lib.mfipm_solve_noalloc(self.h, ctypes.byref(op), _ptr(b), float(tau), _ptr(x), _ptr(state),
+                                              ctypes.byref(info))
+        _check("mfipm_solve_noalloc", rc)
+        return info.as_dict()
 
     # -- batches ----------------------------------------------------------------
     def solve_batched(self, b_packed, tau, n_off, m_off, A_packed=None, a_off=None, rows=None,

@@ -56,7 +56,7 @@ def test_params_default_rejects_null(lib):
 
 
 def test_status_strings(lib):
-    for code in range(-5, 8):
+    for code in range(-6, 8):
         s = lib.mfipm_status_string(code)
         assert s and s != b"unknown", code
     assert lib.mfipm_status_string(99) == b"unknown"
