@@ -48,16 +48,18 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 METRIC = "l1-LS solves/sec + PCG matvec HBM GB/s (% peak), batched & grad vs plain"
 
 
-def alg_bytes(kind: str, n: int, m: int, info: dict) -> float:
+def alg_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
     op = 16.0 * (n + m) if kind == "pdct" else 8.0 * m * n
-    pcg = info["pcg_iters"] * (112.0 * n + op)
+    vec = 56.0 * n if reduced else 112.0 * n  # reduced: x, r, p, Theta_bar^{-1} are n-vectors
+    pcg = info["pcg_iters"] * (vec + op)
     ipm = (info["ipm_iters"] + info["correctors"] + 1) * (160.0 * n + op)
     return pcg + ipm
 
 
-def adjoint_bytes(kind: str, n: int, m: int, info: dict) -> float:
+def adjoint_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
     op = 16.0 * (n + m) if kind == "pdct" else 8.0 * m * n
-    return info["pcg_iters"] * (112.0 * n + op) + 2 * (160.0 * n + op)
+    vec = 56.0 * n if reduced else 112.0 * n
+    return info["pcg_iters"] * (vec + op) + 2 * (160.0 * n + op)
 
 
 def kernel_src_hash() -> str:
@@ -135,6 +137,12 @@ def _hbm_roofline(ab, kernel_ms, kernel, workload):
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
             "kernel": kernel, "alg_bytes_per_launch": ab}
+
+
+def _params(args):
+    """Solver parameters of the run: the paper's defaults, or the reduced
+    n x n PCG system (--reduced)."""
+    return {"reduced": 1} if getattr(args, "reduced", False) else {}
 
 
 def _timed(run, args, torch):
@@ -251,8 +259,9 @@ def make_single(name: str):
 
 def bench_single(args, torch, Solver):
     kind, inst, wl = make_single(args.workload)
+    wl += "_reduced" if args.reduced else ""
     dev = torch.device("cuda", 0)
-    solver = Solver(device=dev)
+    solver = Solver(device=dev, params=_params(args))
     try:
         solver.set_launch(args.workgroups, 0, args.tile)
         b = torch.from_numpy(inst.b).to(dev)
@@ -271,13 +280,13 @@ def bench_single(args, torch, Solver):
         print(f"bench.py: solve did not converge: {info}", file=sys.stderr)
     n, m = inst.n, inst.m
     kms_mean = float(np.mean(kms))
-    cfg = {"workload": wl, "n": n, "m": m, "tau": inst.tau, "tol": 1e-8, "tolpcg": 1e-2,
+    cfg = {"workload": wl, "n": n, "m": m, "tau": inst.tau, "tol": 1e-8, "tolpcg": 1e-2, "reduced": int(args.reduced),
            "ipm_iters": info["ipm_iters"], "pcg_iters": info["pcg_iters"], "correctors": info["correctors"],
            "nmat": info["nmat"], "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
            "kernel_ms_min": round(float(np.min(kms)), 4)}
     kern = "k_mfipm<OpPdct,0>" if kind == "pdct" else "k_mfipm<OpDense,0>"
     out = _line(round(args.steps / wall, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
-                _hbm_roofline(alg_bytes(kind, n, m, info), kms_mean, kern, wl))
+                _hbm_roofline(alg_bytes(kind, n, m, info, args.reduced), kms_mean, kern, wl))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_single(kind, inst, args.cpu_seconds)
     return out
@@ -316,7 +325,7 @@ def bench_batched_dense(args, torch, Solver):
     """The uneven dense batch in one launch, against one launch per instance."""
     sizes, insts, gen_s, dev, n_off, m_off, a_off, A, b, taus = batched_dense_inputs(args, torch)
     del insts
-    solver = Solver(device=dev)
+    solver = Solver(device=dev, params=_params(args))
     try:
         solver.set_launch(args.workgroups, args.team, args.tile)
         run = lambda: solver.solve_batched(b, taus, n_off, m_off, A_packed=A, a_off=a_off)  # noqa: E731
@@ -371,7 +380,7 @@ def bench_grad(args, torch, Solver):
     rows = torch.from_numpy(inst.rows).to(dev)
     b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
     xt = torch.from_numpy(inst.x_true.reshape(-1)).to(dev)
-    solver = Solver(device=dev)
+    solver = Solver(device=dev, params=_params(args))
     try:
         solver.set_launch(args.workgroups, args.team, args.tile)
 
@@ -406,11 +415,11 @@ def bench_grad(args, torch, Solver):
     finally:
         solver.close()
     infos = r.infos
-    ab_f = sum(alg_bytes("pdct", n, m, i) for i in infos)
-    ab_b = sum(adjoint_bytes("pdct", n, m, i) for i in binf)
+    ab_f = sum(alg_bytes("pdct", n, m, i, args.reduced) for i in infos)
+    ab_b = sum(adjoint_bytes("pdct", n, m, i, args.reduced) for i in binf)
     f_mean, b_mean = float(np.mean(fms)), float(np.mean(bms))
     value = B * args.steps / wall
-    wl = f"grad_pdct_batch{B}_n{n}_m{m}"
+    wl = f"grad_pdct_batch{B}_n{n}_m{m}" + ("_reduced" if args.reduced else "")
     cfg = {"workload": wl, "forward_kernel_ms": round(f_mean, 3), "backward_kernel_ms": round(b_mean, 3),
            "ipm_iters": [i["ipm_iters"] for i in infos], "adjoint_pcg_iters": [i["pcg_iters"] for i in binf],
            "not_converged": [j for j, i in enumerate(infos) if i["status"] != 0],
@@ -438,7 +447,7 @@ def bench_shared_dense(args, torch, Solver):
     m_off = np.arange(B + 1, dtype=np.int64) * m
     A = torch.from_numpy(inst.A).to(dev)
     b = torch.from_numpy(inst.b.reshape(-1)).to(dev)
-    solver = Solver(device=dev)
+    solver = Solver(device=dev, params=_params(args))
     try:
         solver.set_launch(args.workgroups, 0, 0)
         run = lambda: solver.solve_batched(b, inst.tau, n_off, m_off, A_packed=A, shared_op=True)  # noqa: E731
@@ -480,7 +489,7 @@ def tune_workload(args, torch, Solver):
     the gradient batch) and writes it to the package's shipped table."""
     from paper_1208_5435_amd import autotune
     dev = torch.device("cuda", 0)
-    solver = Solver(device=dev)
+    solver = Solver(device=dev, params=_params(args))
     out = args.tune_out or autotune.SHIPPED
     jobs = []
     if args.workload in ("pdct", "pdct_hdr", "dense"):
@@ -543,6 +552,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the one-launch-per-instance comparison (profiling runs)")
+    ap.add_argument("--reduced", action="store_true",
+                    help="PCG on the reduced n x n system (half the vector traffic per PCG iteration)")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--tune", action="store_true",

@@ -114,6 +114,17 @@ typedef struct {
   double tolpcg_adj;     /* adjoint PCG tolerance                                 */
   int32_t mxiterpcg_adj; /* adjoint PCG iteration cap                             */
   double step_min;       /* STEP_UNDERFLOW when both steps fall below this        */
+  int32_t reduced;       /* 0: PCG on the 2n system (eq. (eq:ne2_matrix)) with the
+                            block preconditioner (eq. (eq:ne2_P)), as in the paper;
+                            1: PCG on the n x n system behind the Theorem
+                            (thm:ne2_prec) of Section 4,
+                            (Theta_bar^{-1} + A^T A) d = Theta_bar^{-1}
+                            (Theta_u r_u - Theta_v r_v), Theta_bar = Theta_u +
+                            Theta_v, preconditioned by Theta_bar^{-1} + rho I, the
+                            2n direction back-substituted from d = du - dv (half
+                            the vector traffic per PCG iteration; different PCG
+                            iterates).  Lock-step batches use the 2n system and
+                            are not taken when this is set.                     */
 } mfipm_params;
 
 /* Per-instance report (HOST memory). */

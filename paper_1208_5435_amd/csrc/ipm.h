@@ -28,6 +28,7 @@ struct DevParams {
   double tolpcg_adj;
   int32_t mxiterpcg_adj;
   double step_min;
+  int32_t reduced;
 };
 
 struct DevInfo {
@@ -189,6 +190,78 @@ struct FPcgC2 {
   }
 };
 
+// The reduced system (Section 4, Theorem (thm:ne2_prec)): with
+// d = dz_u - dz_v the two block rows of (eq:ne2_H) give
+// (Theta_bar^{-1} + A^T A) d = Theta_bar^{-1} (Theta_u r_u - Theta_v r_v),
+// Theta_bar = Theta_u + Theta_v, preconditioned by Theta_bar^{-1} + rho I.
+// In Theta^{-1} entries (tu, tv): Theta_bar^{-1} = tu tv / (tu + tv), the
+// right-hand side is (tv r_u - tu r_v) / (tu + tv), and the 2n direction
+// follows without an operator product: du = (r_u + r_v + tv d) / (tu + tv),
+// dv = du - d.  PCG vectors are n-vectors (x, r, p, Theta_bar^{-1}), the
+// operator input is p itself.
+struct RedVec {
+  double* X;   // PCG solution d
+  double* R;   // reduced residual
+  double* P;   // direction
+  double* TB;  // Theta_bar^{-1}
+};
+__device__ __forceinline__ RedVec red_vec(const TeamWS& w, long n) {
+  RedVec v;
+  v.X = reinterpret_cast<double*>(w.X);
+  v.TB = v.X + n;
+  v.P = reinterpret_cast<double*>(w.P);
+  v.R = v.P + n;
+  return v;
+}
+__device__ __forceinline__ double red_tbar(double tu, double tv) { return tu * tv / (tu + tv); }
+__device__ __forceinline__ double red_rhs(double tu, double tv, double ru, double rv) {
+  return (tv * ru - tu * rv) / (tu + tv);
+}
+__device__ __forceinline__ double2 red_back(double tu, double tv, double ru, double rv, double d) {
+  const double du = (ru + rv + tv * d) / (tu + tv);
+  return make_double2(du, du - d);
+}
+
+// PCG pass C on the reduced system: as FPcgC2 with n-vectors,
+// y = r / (Theta_bar^{-1} + rho), q = Theta_bar^{-1} p + t; returns y'.
+struct FPcgRed {
+  static constexpr int K = 5;
+  static constexpr bool CHAIN = true;
+  struct In {
+    double p, tb, x, r;
+  };
+  RedVec v;
+  double alpha, beta, rho;
+  int first;
+  double acc[K];
+  __device__ void reset() {
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc[j] = 0.0;
+  }
+  __device__ void load(long i, In& in) const {
+    if (!first) in.p = v.P[i];
+    in.tb = v.TB[i];
+    in.x = v.X[i];
+    in.r = v.R[i];
+  }
+  __device__ double scatter(long i, double t, const In& in) {
+    const double y = in.r / (in.tb + rho);
+    const double p = first ? y : y + beta * in.p;
+    const double q = in.tb * p + t;
+    const double x = in.x + alpha * p, r = in.r - alpha * q;
+    v.X[i] = x;
+    v.R[i] = r;
+    v.P[i] = p;
+    const double yn = r / (in.tb + rho);
+    acc[0] += r * yn;
+    acc[1] += r * r;
+    acc[2] += in.tb * yn * yn;
+    acc[3] += in.tb * yn * p;
+    acc[4] += in.tb * p * p;
+    return yn;
+  }
+};
+
 // Residual pass A: bring (z, s) up to date (initial point, pending step) or
 // form the trial point of the corrector; d = x = u - v.
 // acc0 += 1^T z, acc1 += z^T s.  As an elementwise functor (elem) it serves
@@ -247,7 +320,8 @@ struct FResA {
 // point), r = rhs, x = 0.  acc0 = max |g|, acc1 += rhs^T rhs,
 // acc2 += rhs^T P^{-1} rhs, acc3 += y^T Theta^{-1} y with y = P^{-1} rhs;
 // returns y_u - y_v, the first PCG direction's gather.
-struct FResC {
+template <bool RED>
+struct FResCT {
   static constexpr int K = 4;
   static constexpr bool CHAIN = true;
   struct In {
@@ -260,6 +334,7 @@ struct FResC {
   double2* TI;
   double2* R;
   double2* X;
+  RedVec v;  // reduced system (RED)
   double tau, sigma, mu, aP, aD, rho;
   int trial;
   double acc[K];
@@ -290,14 +365,28 @@ struct FResC {
     const double fsu = sigma * mu - zt.x * st.x, fsv = sigma * mu - zt.y * st.y;
     const double ru = fzu + fsu / in.z.x, rv = fzv + fsv / in.z.y;
     R[i] = make_double2(ru, rv);
-    X[i] = make_double2(0.0, 0.0);
     acc[0] = fmax(acc[0], fabs(g));
-    acc[1] += ru * ru + rv * rv;
-    double yu, yv;
-    precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
-    acc[2] += ru * yu + rv * yv;
-    acc[3] += ti.x * yu * yu + ti.y * yv * yv;
-    return yu - yv;  // first gather of the PCG that follows
+    if constexpr (RED) {
+      // the reduced right-hand side; R keeps the 2n one for the back-substitution
+      const double tb = red_tbar(ti.x, ti.y);
+      if (!trial) v.TB[i] = tb;
+      const double rb = red_rhs(ti.x, ti.y, ru, rv);
+      v.R[i] = rb;
+      v.X[i] = 0.0;
+      const double y = rb / (tb + rho);
+      acc[1] += rb * rb;
+      acc[2] += rb * y;
+      acc[3] += tb * y * y;
+      return y;
+    } else {
+      X[i] = make_double2(0.0, 0.0);
+      acc[1] += ru * ru + rv * rv;
+      double yu, yv;
+      precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
+      acc[2] += ru * yu + rv * yv;
+      acc[3] += ti.x * yu * yu + ti.y * yv * yv;
+      return yu - yv;  // first gather of the PCG that follows
+    }
   }
 };
 
@@ -307,17 +396,20 @@ struct FResC {
 // over dz < 0 of -z/dz, acc1 likewise for s.  Run as a gather pass, it hands
 // dz_u - dz_v to the operator's first stage, whose result (the transform of
 // the x-direction) the next residual combines by linearity.
-struct FStep {
+template <bool RED>
+struct FStepT {
   static constexpr int K = 2;
   struct In {
     double2 z, s, ti, x, dz, ds;
+    double d;
   };
   double2* Z;
   double2* S;
   double2* TI;
-  double2* X;
+  double2* X;  // 2n: the PCG solution; reduced: the 2n right-hand side
   double2* DZ;
   double2* DS;
+  const double* Xr;  // reduced: the PCG solution d
   double sigma, mu;      // predictor: sigma, mu; corrector: sigma3, mu~
   double aPp, aDp;       // predictor step sizes (corrector only)
   int corr;
@@ -328,23 +420,26 @@ struct FStep {
     in.s = S[i];
     in.ti = TI[i];
     in.x = X[i];
+    if constexpr (RED) in.d = Xr[i];
     if (corr) {
       in.dz = DZ[i];
       in.ds = DS[i];
     }
   }
   __device__ double gather(long i, const In& in) {
+    // the Newton direction of this solve (2n, or back-substituted from d)
+    const double2 sol = RED ? red_back(in.ti.x, in.ti.y, in.x.x, in.x.y, in.d) : in.x;
     double2 dz, ds;
     if (!corr) {
-      dz = in.x;
+      dz = sol;
       const double fsu = sigma * mu - in.z.x * in.s.x, fsv = sigma * mu - in.z.y * in.s.y;
       ds = make_double2(fsu / in.z.x - in.ti.x * dz.x, fsv / in.z.y - in.ti.y * dz.y);
     } else {
       const double ztu = in.z.x + aPp * in.dz.x, ztv = in.z.y + aPp * in.dz.y;
       const double stu = in.s.x + aDp * in.ds.x, stv = in.s.y + aDp * in.ds.y;
       const double fsu = sigma * mu - ztu * stu, fsv = sigma * mu - ztv * stv;
-      const double dsu = fsu / in.z.x - in.ti.x * in.x.x, dsv = fsv / in.z.y - in.ti.y * in.x.y;
-      dz = make_double2(in.dz.x + in.x.x, in.dz.y + in.x.y);
+      const double dsu = fsu / in.z.x - in.ti.x * sol.x, dsv = fsv / in.z.y - in.ti.y * sol.y;
+      dz = make_double2(in.dz.x + sol.x, in.dz.y + sol.y);
       ds = make_double2(in.ds.x + dsu, in.ds.y + dsv);
     }
     DZ[i] = dz;
@@ -375,7 +470,8 @@ struct FOut {
 // r = rhs = [g; -g], x = 0, and the first PCG gather d = y_u - y_v with
 // y = P^{-1} rhs.  acc0 += rhs^T P^{-1} rhs, acc1 += rhs^T rhs,
 // acc2 += y^T Theta^{-1} y.
-struct FBwdInit {
+template <bool RED>
+struct FBwdInitT {
   static constexpr int K = 3;
   struct In {
     double2 z, s;
@@ -387,6 +483,7 @@ struct FBwdInit {
   double2* TI;
   double2* R;
   double2* X;
+  RedVec v;
   double rho;
   double acc[K];
   __device__ void reset() { acc[0] = acc[1] = acc[2] = 0.0; }
@@ -400,29 +497,58 @@ struct FBwdInit {
     TI[i] = ti;
     const double ru = in.g, rv = -in.g;
     R[i] = make_double2(ru, rv);
-    X[i] = make_double2(0.0, 0.0);
-    double yu, yv;
-    precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
-    acc[0] += ru * yu + rv * yv;
-    acc[1] += ru * ru + rv * rv;
-    acc[2] += ti.x * yu * yu + ti.y * yv * yv;
-    return yu - yv;
+    if constexpr (RED) {
+      // reduced right-hand side of [g; -g]: (tv g + tu g) / (tu + tv) = g
+      const double tb = red_tbar(ti.x, ti.y);
+      v.TB[i] = tb;
+      const double rb = red_rhs(ti.x, ti.y, ru, rv);
+      v.R[i] = rb;
+      v.X[i] = 0.0;
+      const double y = rb / (tb + rho);
+      acc[0] += rb * y;
+      acc[1] += rb * rb;
+      acc[2] += tb * y * y;
+      return y;
+    } else {
+      X[i] = make_double2(0.0, 0.0);
+      double yu, yv;
+      precond_apply(ti.x, ti.y, rho, ru, rv, yu, yv);
+      acc[0] += ru * yu + rv * yv;
+      acc[1] += ru * ru + rv * rv;
+      acc[2] += ti.x * yu * yu + ti.y * yv * yv;
+      return yu - yv;
+    }
   }
 };
 
-// Adjoint output gather: d = w_u - w_v; acc0 += 1^T w.
-struct FBwdGather {
+// Adjoint output gather: d = w_u - w_v; acc0 += 1^T w (reduced: w from the
+// back-substitution of [g; -g] with d = the PCG solution).
+template <bool RED>
+struct FBwdGatherT {
   static constexpr int K = 1;
   struct In {
-    double2 w;
+    double2 w, ti, r;
+    double d;
   };
   double2* W;
+  const double2* TI;
+  const double2* R;
+  const double* Xr;
   double acc[K];
   __device__ void reset() { acc[0] = 0.0; }
-  __device__ void load(long i, In& in) const { in.w = W[i]; }
+  __device__ void load(long i, In& in) const {
+    if constexpr (RED) {
+      in.ti = TI[i];
+      in.r = R[i];
+      in.d = Xr[i];
+    } else {
+      in.w = W[i];
+    }
+  }
   __device__ double gather(long i, const In& in) {
-    acc[0] += in.w.x + in.w.y;
-    return in.w.x - in.w.y;
+    const double2 w = RED ? red_back(in.ti.x, in.ti.y, in.r.x, in.r.y, in.d) : in.w;
+    acc[0] += w.x + w.y;
+    return w.x - w.y;
   }
 };
 
@@ -746,7 +872,7 @@ __device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& a
 //           partial dot products for beta and p^T Theta^{-1} p.
 // Returns a status (0 = ok); *iters = operator applies.
 // ------------------------------------------------------------------------
-template <class OP>
+template <class OP, bool RED>
 __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double rho, double tol, int maxit,
                                        double rhs2, double gamma, double yty, int* iters, int* capped = nullptr) {
   const int kB[1] = {0};
@@ -778,16 +904,26 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
       status = isfinite(pq) ? ST_PCG_BREAKDOWN : ST_NONFINITE;
       break;
     }
-    FPcgC2 fc;
-    fc.P = w.P;
-    fc.TI = w.TI;
-    fc.X = w.X;
-    fc.R = w.R;
-    fc.rho = rho;
-    fc.alpha = gamma / pq;
-    fc.beta = beta;
-    fc.first = first;
-    run_C(cx, op, fc, kC, w.partC);
+    if constexpr (RED) {
+      FPcgRed fc;
+      fc.v = red_vec(w, op.n);
+      fc.rho = rho;
+      fc.alpha = gamma / pq;
+      fc.beta = beta;
+      fc.first = first;
+      run_C(cx, op, fc, kC, w.partC);
+    } else {
+      FPcgC2 fc;
+      fc.P = w.P;
+      fc.TI = w.TI;
+      fc.X = w.X;
+      fc.R = w.R;
+      fc.rho = rho;
+      fc.alpha = gamma / pq;
+      fc.beta = beta;
+      fc.first = first;
+      run_C(cx, op, fc, kC, w.partC);
+    }
     if (team_barrier(cx.t)) {
       status = ST_ABORTED;
       break;
@@ -811,7 +947,7 @@ struct ResOut {
   int status;
 };
 
-template <class OP>
+template <class OP, bool RED>
 __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w, double2* Z, double2* S, const DevParams& prm,
                                int mode, double aP, double aD, double tau, double sigma, double sigma3,
                                int trial, double rho) {
@@ -866,7 +1002,8 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
   o.zs = pA[1];
   o.rb2 = pB[0];
   o.brb = pB[1];
-  FResC fc;
+  FResCT<RED> fc;
+  fc.v = red_vec(w, op.n);
   fc.Z = Z;
   fc.S = S;
   fc.DZ = w.DZ;
@@ -896,7 +1033,7 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
   return o;
 }
 
-template <class OP>
+template <class OP, bool RED>
 __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
   const InstDesc d = a.inst[ii];
   const TeamWS w = make_ws(a, cx.t.id);
@@ -927,7 +1064,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
       // sigma for this iteration from the previous step sizes
       const double sigma = (k != 1 && (aP_prev <= prm.alpha_bar || aD_prev <= prm.alpha_bar)) ? prm.sigma2
                                                                                                : prm.sigma1;
-      ResOut ro = residual_rhs(cx, op, w, Z, S, prm, mode, aP, aD, tau, sigma, prm.sigma3, 0, rho);
+      ResOut ro = residual_rhs<OP, RED>(cx, op, w, Z, S, prm, mode, aP, aD, tau, sigma, prm.sigma3, 0, rho);
       nmat += 2;
       if (ro.status) {
         status = ro.status;
@@ -951,18 +1088,19 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
         break;
       }
       int its = 0;
-      st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, ro.yty, &its);
+      st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, ro.yty, &its);
       pcg_total += its;
       nmat += 2 * its;
       if (st) {
         status = st;
         break;
       }
-      FStep fs;
+      FStepT<RED> fs;
       fs.Z = Z;
       fs.S = S;
       fs.TI = w.TI;
-      fs.X = w.X;
+      fs.X = RED ? w.R : w.X;
+      fs.Xr = red_vec(w, n).X;
       fs.DZ = w.DZ;
       fs.DS = w.DS;
       fs.sigma = sigma;
@@ -982,13 +1120,13 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
       aD = fmin(1.0, prm.eta * rs[1]);
       if (aP <= prm.alpha_tilde || aD <= prm.alpha_tilde) {
         // corrector: residuals at the trial point with sigma3, same H and P
-        ResOut rc = residual_rhs(cx, op, w, Z, S, prm, RA_TRIAL, aP, aD, tau, sigma, prm.sigma3, 1, rho);
+        ResOut rc = residual_rhs<OP, RED>(cx, op, w, Z, S, prm, RA_TRIAL, aP, aD, tau, sigma, prm.sigma3, 1, rho);
         nmat += 2;
         if (rc.status) {
           status = rc.status;
           break;
         }
-        st = pcg_run(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, rc.yty, &its);
+        st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, rc.yty, &its);
         pcg_total += its;
         nmat += 2 * its;
         if (st) {
@@ -1062,7 +1200,7 @@ __device__ __forceinline__ void op_forward_gather(Ctx& cx, OpPdct& op, const Tea
 
 // Adjoint: (Theta^{-1} + F F^T) w = [g; -g] at the stored state, then
 // grad_b = A (w_u - w_v), grad_tau = -1^T w.
-template <class OP>
+template <class OP, bool RED>
 __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int ii, char* lds) {
   const InstDesc d = a.inst[ii];
   const TeamWS w = make_ws(a, cx.t.id);
@@ -1082,7 +1220,8 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
     if (ab) st = status = ST_ABORTED;
   }
   if (!st) {
-    FBwdInit fi;
+    FBwdInitT<RED> fi;
+    fi.v = red_vec(w, n);
     fi.Z = Z;
     fi.S = S;
     fi.gx = a.grad_x + d.n_off;
@@ -1095,11 +1234,15 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
     if (team_barrier(cx.t)) st = ST_ABORTED;
     double pI[3];
     reduce_items<3>(kI, w.partA, op.nA(), pI, cx.red);
-    if (!st) st = pcg_run(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its, &capped);
+    if (!st)
+      st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its, &capped);
     status = st;
     if (!st) {
-      FBwdGather fg;
+      FBwdGatherT<RED> fg;
       fg.W = w.X;
+      fg.TI = w.TI;
+      fg.R = w.R;
+      fg.Xr = red_vec(w, n).X;
       const int kG[1] = {0};
       run_A(cx, op, fg, kG, w.partA);
       if (team_barrier(cx.t)) status = ST_ABORTED;

@@ -27,7 +27,7 @@ static_assert(sizeof(DevInfo) == sizeof(mfipm_info), "info mirror");
 // ------------------------------------------------------------------------
 // kernels
 // ------------------------------------------------------------------------
-template <class OP, int BWD>
+template <class OP, int BWD, bool RED>
 __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds_dyn[];
   __shared__ double red[MF_RED_DOUBLES];
@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
     const int q = ld_flag(w.slot);
     if (q >= a.batch) break;
     const int ii = a.order[q];
-    if (BWD) backward_instance<OP>(cx, a, ii, lds_dyn);
-    else solve_instance<OP>(cx, a, ii, lds_dyn);
+    if (BWD) backward_instance<OP, RED>(cx, a, ii, lds_dyn);
+    else solve_instance<OP, RED>(cx, a, ii, lds_dyn);
   }
 }
 
@@ -91,9 +91,9 @@ struct mfipm_handle {
   int req_wg, req_team, req_tile;
   hipEvent_t ev0, ev1;
   double last_ms;
-  int occ[2][2];             // [op][bwd] max resident workgroups per CU
+  int occ[2][2][2];          // [op][bwd][reduced] max resident workgroups per CU
   int occ_ls;                // the same for the lock-step kernel
-  size_t scratch_lane[2][2];  // [op][bwd] private bytes per lane
+  size_t scratch_lane[2][2][2];  // [op][bwd][reduced] private bytes per lane
   // twiddle tables (device, owned by the handle), one per table resolution
   cplx* tw[32];
   // pinned host staging for the per-call uploads and read-backs
@@ -123,6 +123,7 @@ int check_params(const mfipm_params* p) {
         p->sigma3 <= 1))
     return MFIPM_ERR_INVALID_ARG;
   if (std::isnan(p->rho)) return MFIPM_ERR_INVALID_ARG;
+  if (p->reduced != 0 && p->reduced != 1) return MFIPM_ERR_INVALID_ARG;
   return MFIPM_OK;
 }
 
@@ -217,25 +218,29 @@ GlobalLayout global_layout(int op_kind, long long n_max, int batch, int teams, c
 
 // Chunk capacity of the dense fused path: one chunk per workgroup of a
 // single-instance team (up to the resident grid), at most 64 for batches.
-int pt_chunks_for(const mfipm_handle* h, int bwd, int batch, long long m_max) {
+int pt_chunks_for(const mfipm_handle* h, int bwd, int batch, long long m_max, int red) {
   const long long blocks = (m_max + DN_FB - 1) / DN_FB;
-  const long long gmax = std::max(1, h->occ[MFIPM_OP_DENSE][bwd] * h->num_cu);
+  const long long gmax = std::max(1, h->occ[MFIPM_OP_DENSE][bwd][red] * h->num_cu);
   const long long cap = batch == 1 ? gmax : 64;
   return (int)std::max(1LL, std::min(blocks, cap));
 }
 
-int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch) {
-  const int gmax = std::max(1, h->occ[op_kind][bwd] * h->num_cu);
+int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch, int red) {
+  const int gmax = std::max(1, h->occ[op_kind][bwd][red] * h->num_cu);
   return std::max(1, std::min(batch, gmax));
 }
 
-template <class OP, int BWD>
+template <class OP, int BWD, bool RED>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&k_mfipm<OP, BWD>);
+  return reinterpret_cast<const void*>(&k_mfipm<OP, BWD, RED>);
 }
-const void* pick_kernel(int op_kind, int bwd) {
-  if (op_kind == MFIPM_OP_DENSE) return bwd ? kernel_ptr<OpDense, 1>() : kernel_ptr<OpDense, 0>();
-  return bwd ? kernel_ptr<OpPdct, 1>() : kernel_ptr<OpPdct, 0>();
+template <bool RED>
+const void* pick_kernel_r(int op_kind, int bwd) {
+  if (op_kind == MFIPM_OP_DENSE) return bwd ? kernel_ptr<OpDense, 1, RED>() : kernel_ptr<OpDense, 0, RED>();
+  return bwd ? kernel_ptr<OpPdct, 1, RED>() : kernel_ptr<OpPdct, 0, RED>();
+}
+const void* pick_kernel(int op_kind, int bwd, int red) {
+  return red ? pick_kernel_r<true>(op_kind, bwd) : pick_kernel_r<false>(op_kind, bwd);
 }
 // Dynamic LDS: dense reduction scratch; partial DCT tile + twiddle tables
 // (lo_bits / hi entries of the call, or the largest supported, n = 2^20).
@@ -408,8 +413,9 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   if (bwd && (!grad_x || !grad_b || !grad_tau)) return MFIPM_ERR_INVALID_ARG;
 
   // launch shape
-  if (h->occ[P.op_kind][bwd] < 1) return MFIPM_ERR_HIP;
-  const int gmax = std::max(1, h->occ[P.op_kind][bwd] * h->num_cu);
+  const int red = h->prm.reduced;
+  if (h->occ[P.op_kind][bwd][red] < 1) return MFIPM_ERR_HIP;
+  const int gmax = std::max(1, h->occ[P.op_kind][bwd][red] * h->num_cu);
   int team_size, num_teams;
   if (P.batch == 1) {
     long long want = h->req_wg > 0 ? h->req_wg : widest_pass(P.op_kind, P.n_max, P.m_max, h->req_tile);
@@ -425,12 +431,12 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     num_teams = std::max(1, std::min(P.batch, total / team_size));
   }
   if (team_size > MF_MAX_TEAM) team_size = MF_MAX_TEAM;
-  const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch);
+  const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch, red);
   if (num_teams > teams_bound) num_teams = teams_bound;
-  if (h->scratch_lane[P.op_kind][bwd] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
+  if (h->scratch_lane[P.op_kind][bwd][red] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
     return MFIPM_ERR_HIP;
 
-  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max));
+  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max, red));
   GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
   if (ws_bytes < gl.total) return noalloc ? MFIPM_ERR_TOO_LARGE : MFIPM_ERR_WORKSPACE_TOO_SMALL;
   int tw_log2n_max = ilog2_host(P.n_max);
@@ -539,7 +545,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   void* args[] = {&a};
   const int grid = num_teams * team_size;
   if (hipEventRecord(h->ev0, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
-  if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd), dim3(grid), dim3(MF_THREADS), args,
+  if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd, red), dim3(grid), dim3(MF_THREADS), args,
                                  (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
     return fail(MFIPM_ERR_HIP);
   if (hipEventRecord(h->ev1, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
@@ -594,7 +600,7 @@ LsLayout ls_layout(long long n, long long m, int B) {
 
 bool use_lockstep(const mfipm_handle* h, int op_kind, int shared_op, int batch) {
   return op_kind == MFIPM_OP_DENSE && shared_op && batch >= kLockstepMinBatch &&
-         batch <= LS_MAX_GROUPS * LS_TN && h->req_team <= 0;
+         batch <= LS_MAX_GROUPS * LS_TN && h->req_team <= 0 && !h->prm.reduced;
 }
 
 int launch_lockstep(mfipm_handle* h, const Problem& P, const double* A, const double* b, double* x, double* state,
@@ -705,6 +711,7 @@ int mfipm_params_default(mfipm_params* p) {
   p->tolpcg_adj = 1e-12;
   p->mxiterpcg_adj = 1000;
   p->step_min = 1e-14;
+  p->reduced = 0;
   return MFIPM_OK;
 }
 
@@ -732,22 +739,23 @@ int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
   }
   h->wall_khz = wclk > 0 ? wclk : 100000;
   for (int op = 0; op < 2; ++op)
-    for (int bwd = 0; bwd < 2; ++bwd) {
+    for (int bwd = 0; bwd < 2; ++bwd)
+      for (int red = 0; red < 2; ++red) {
       int occ = 0;
-      const void* k = pick_kernel(op, bwd);
+      const void* k = pick_kernel(op, bwd, red);
       if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds(op)) != hipSuccess ||
           hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, MF_THREADS, dyn_lds(op)) != hipSuccess) {
         delete h;
         return MFIPM_ERR_HIP;
       }
-      h->occ[op][bwd] = occ;  // 0: this kernel cannot be resident; calls that need it fail
+      h->occ[op][bwd][red] = occ;  // 0: this kernel cannot be resident; calls that need it fail
       hipFuncAttributes fa;
       if (hipFuncGetAttributes(&fa, k) != hipSuccess) {
         delete h;
         return MFIPM_ERR_HIP;
       }
-      h->scratch_lane[op][bwd] = fa.localSizeBytes;
-    }
+      h->scratch_lane[op][bwd][red] = fa.localSizeBytes;
+      }
   {
     const void* k = reinterpret_cast<const void*>(&k_mfipm_lockstep);
     int occ = 0;
@@ -804,11 +812,12 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
   if (!h || !bytes || batch < 1 || max_n < 1 || max_m < 1) return MFIPM_ERR_INVALID_ARG;
   if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
   size_t best = 0;
-  for (int bwd = 0; bwd < 2; ++bwd) {
-    const TeamLayout tl = team_layout(op_kind, max_n, max_m, pt_chunks_for(h, bwd, batch, max_m));
-    const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch), tl);
-    best = std::max(best, gl.total);
-  }
+  for (int bwd = 0; bwd < 2; ++bwd)
+    for (int red = 0; red < 2; ++red) {
+      const TeamLayout tl = team_layout(op_kind, max_n, max_m, pt_chunks_for(h, bwd, batch, max_m, red));
+      const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch, red), tl);
+      best = std::max(best, gl.total);
+    }
   if (op_kind == MFIPM_OP_DENSE && batch >= kLockstepMinBatch) best = std::max(best, ls_layout(max_n, max_m, batch).total);
   *bytes = best;
   return MFIPM_OK;

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("rho", ctypes.c_double),
                 ("z0", ctypes.c_double), ("s0", ctypes.c_double),
                 ("tolpcg_adj", ctypes.c_double), ("mxiterpcg_adj", ctypes.c_int32),
-                ("step_min", ctypes.c_double)]
+                ("step_min", ctypes.c_double), ("reduced", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -104,7 +104,9 @@ def check_against_oracle(op, b, tau, x_gpu, info, state=None, params=None, label
             assert resolve is not None, (label, "escalation needs a GPU re-solve")
             xt, st = resolve(TIGHT)
             tight["gpu"] = (xt, st)
-            tight["ref"] = R.solve(op, b, tau, R.Params(**TIGHT))
+            base = dict(vars(params)) if params is not None else {}
+            base.update(TIGHT)
+            tight["ref"] = R.solve(op, b, tau, R.Params(**base))
         return tight["gpu"], tight["ref"]
 
     bscale = 1.0 + float(np.max(np.abs(b)))
