@@ -19,7 +19,7 @@
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-#define LS_TM 64   // output rows of a GEMM work item
+#define LS_TM 128  // output rows of a GEMM work item
 #define LS_TN 64   // output columns (signals) of a GEMM work item
 #define LS_TK 32   // K chunk staged in LDS per step
 #define LS_PAD 2   // LDS row padding (doubles) against bank conflicts
@@ -36,7 +36,7 @@ struct SigState {
   long nmat;
   double aP_prev, aD_prev, aP, aD;
   double sigma, mu, mu_t;
-  double rhs2, rty;
+  double rhs2, rty, ptp;  // PCG: ||rhs||^2, r^T P^{-1} r, p^T Theta^{-1} p
   double relgap, primal, dual;
 };
 
@@ -74,8 +74,9 @@ struct LArgs {
 // the first product) or M-contiguous (a_kmajor = 1: Aop[c][k] = A[k*lda + c0+c],
 // A^T in the second product).  Bop[k][j] = Bm[(j0+j)*ldb + k] (each signal's
 // column contiguous).  Rows past `M` and columns past `N` read zeros.
-// Eight waves: wave w owns the 16 x 32 block (rows 16 (w/2), columns
-// 32 (w%2) .. +32) as two 16 x 16 accumulators.
+// Eight waves: wave w owns the 32 x 32 block at rows 32 (w/2), columns
+// 32 (w%2), as four 16 x 16 accumulators, so each A and B fragment read from
+// LDS feeds two MFMAs.
 // ---------------------------------------------------------------------------
 struct GemmLDS {
   double a[2][LS_TK][LS_TM + LS_PAD];
@@ -129,15 +130,15 @@ __device__ __forceinline__ void gemm_store_lds(GemmLDS& s, int buf, int a_kmajor
   }
 }
 
-// Accumulates the work item into acc[2] (per wave, see above).
+// Accumulates the work item into acc[4] (per wave, see above).
 __device__ __forceinline__ void gemm_item(GemmLDS& s, const double* __restrict__ A, long lda, int a_kmajor, long i0,
                                           long M, const double* __restrict__ Bm, long ldb, long j0, long N, long k0,
-                                          long k1, double4_t (&acc)[2]) {
+                                          long k1, double4_t (&acc)[4]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int bi = (wave >> 1) * 16, bj = (wave & 1) * 32;
+  const int bi = (wave >> 1) * 32, bj = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  acc[0] = double4_t{0, 0, 0, 0};
-  acc[1] = double4_t{0, 0, 0, 0};
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = double4_t{0, 0, 0, 0};
   double ra[LS_EA], rb[LS_EB];
   gemm_load(A, lda, a_kmajor, i0, M, Bm, ldb, j0, N, k0, k1, ra, rb);
   gemm_store_lds(s, 0, a_kmajor, ra, rb);
@@ -148,11 +149,14 @@ __device__ __forceinline__ void gemm_item(GemmLDS& s, const double* __restrict__
     if (more) gemm_load(A, lda, a_kmajor, i0, M, Bm, ldb, j0, N, k + LS_TK, k1, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < LS_TK; kk += 4) {
-      const double av = s.a[buf][kk + lk][bi + li];
+      const double a0 = s.a[buf][kk + lk][bi + li];
+      const double a1 = s.a[buf][kk + lk][bi + 16 + li];
       const double b0 = s.b[buf][kk + lk][bj + li];
       const double b1 = s.b[buf][kk + lk][bj + 16 + li];
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[1], 0, 0, 0);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
     }
     if (more) gemm_store_lds(s, buf ^ 1, a_kmajor, ra, rb);
     __syncthreads();
@@ -160,19 +164,19 @@ __device__ __forceinline__ void gemm_item(GemmLDS& s, const double* __restrict__
   }
 }
 
-// Writes the wave's two accumulators: C[(j0 + j) * ldc + i0 + i] for the
+// Writes the wave's four accumulators: C[(j0 + j) * ldc + i0 + i] for the
 // columns in [j0, N) and rows in [i0, M).
 __device__ __forceinline__ void gemm_store(double* C, long ldc, long i0, long M, long j0, long N,
-                                           const double4_t (&acc)[2]) {
+                                           const double4_t (&acc)[4]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int bi = (wave >> 1) * 16, bj = (wave & 1) * 32;
+  const int bi = (wave >> 1) * 32, bj = (wave & 1) * 32;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const long j = j0 + bj + 16 * h + (lane & 15);
+  for (int h = 0; h < 4; ++h) {
+    const long j = j0 + bj + 16 * (h & 1) + (lane & 15);
     if (j >= N) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const long i = i0 + bi + (lane >> 4) + 4 * r;
+      const long i = i0 + bi + 16 * (h >> 1) + (lane >> 4) + 4 * r;
       if (i < M) C[j * ldc + i] = acc[h][r];
     }
   }
@@ -281,8 +285,8 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
         st.sigma = (st.k != 1 && (st.aP_prev <= prm.alpha_bar || st.aD_prev <= prm.alpha_bar)) ? prm.sigma2
                                                                                                : prm.sigma1;
         // rhs = f_z + Z^{-1} f_s (eqs. (fzfs), (redNewton)), Theta^{-1} = s / z
-        double w[2] = {0.0, 0.0};
-        const int k2[2] = {0, 0};
+        double w[3] = {0.0, 0.0, 0.0};
+        const int k3[3] = {0, 0, 0};
         const double sm = st.sigma * st.mu;
         for (long i = tid; i < n; i += MF_THREADS) {
           const double2 z = g.Z[i], s = g.S[i];
@@ -299,10 +303,12 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
           g.d[i] = yu - yv;
           w[0] += ru * ru + rv * rv;
           w[1] += ru * yu + rv * yv;
+          w[2] += ti.x * yu * yu + ti.y * yv * yv;
         }
-        wg_allreduce<2>(k2, w, g.red);
+        wg_allreduce<3>(k3, w, g.red);
         st.rhs2 = w[0];
         st.rty = w[1];
+        st.ptp = w[2];
         st.corr = 0;
         st.pcg_it = 0;
         rr = st.rhs2;
@@ -321,8 +327,8 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
       wg_allreduce<1>(k1, v, g.red);
       st.mu_t = v[0] / (2.0 * (double)n);
       const double sm = prm.sigma3 * st.mu_t;
-      double w[2] = {0.0, 0.0};
-      const int k2[2] = {0, 0};
+      double w[3] = {0.0, 0.0, 0.0};
+      const int k3[3] = {0, 0, 0};
       for (long i = tid; i < n; i += MF_THREADS) {
         const double2 z = g.Z[i], s = g.S[i], dz = g.DZ[i], ds = g.DS[i], ti = g.TI[i];
         const double gi = g.t[i];
@@ -338,28 +344,30 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
         g.d[i] = yu - yv;
         w[0] += ru * ru + rv * rv;
         w[1] += ru * yu + rv * yv;
+        w[2] += ti.x * yu * yu + ti.y * yv * yv;
       }
-      wg_allreduce<2>(k2, w, g.red);
+      wg_allreduce<3>(k3, w, g.red);
       st.rhs2 = w[0];
       st.rty = w[1];
+      st.ptp = w[2];
       st.corr = 1;
       st.pcg_it = 0;
       rr = st.rhs2;
     }
   } else if (st.phase == PH_PCG) {
-    // one PCG iteration with t = A^T A (p_u - p_v)  (Section 4)
+    // one PCG iteration with t = A^T A d, d = p_u - p_v (Section 4):
+    // p^T H p = p^T Theta^{-1} p + ||A d||^2, the latter from the column A d
     st.pcg_it += 1;
     st.pcg_total += 1;
     st.nmat += 2;
     double v[1] = {0.0};
     const int k1[1] = {0};
-    for (long i = tid; i < n; i += MF_THREADS) {
-      const double2 p = g.P[i], ti = g.TI[i];
-      const double t = g.t[i];
-      v[0] += p.x * (ti.x * p.x + t) + p.y * (ti.y * p.y - t);
+    for (long i = tid; i < m; i += MF_THREADS) {
+      const double yy = g.y[i];
+      v[0] += yy * yy;
     }
     wg_allreduce<1>(k1, v, g.red);
-    const double pq = v[0];
+    const double pq = st.ptp + v[0];
     if (!(pq > 0.0)) {
       st.status = isfinite(pq) ? ST_PCG_BREAKDOWN : ST_NONFINITE;
       done = 1;
@@ -384,9 +392,10 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
       const double rty_new = w[1];
       const double beta = rty_new / st.rty;
       st.rty = rty_new;
-      // the new direction (used only if the PCG goes on)
+      // the new direction (used only if the PCG goes on) and its p^T Theta^{-1} p
       const bool go = isfinite(rr) && !(rr <= prm.tolpcg * prm.tolpcg * st.rhs2) && st.pcg_it != prm.mxiterpcg;
       if (go) {
+        double u[1] = {0.0};
         for (long i = tid; i < n; i += MF_THREADS) {
           const double2 p = g.P[i], ti = g.TI[i], r = g.R[i];
           double yu, yv;
@@ -394,7 +403,10 @@ __device__ __forceinline__ void sig_advance(const LArgs& a, const InstDesc* inst
           const double2 pn = make_double2(yu + beta * p.x, yv + beta * p.y);
           g.P[i] = pn;
           g.d[i] = pn.x - pn.y;
+          u[0] += ti.x * pn.x * pn.x + ti.y * pn.y * pn.y;
         }
+        wg_allreduce<1>(k1, u, g.red);
+        st.ptp = u[0];
       }
     }
   }
@@ -613,12 +625,18 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm_lockstep(LArgs a) {
     __syncthreads();
     const int nact = s_nact;
     if (nact == 0) break;
-    // first product, per K slice: Yp[s] = A[:, slice] D[slice, :]
-    const int items1 = nact * mt1 * LS_SPLIT;
+    // first product, per K slice: Yp[s] = A[:, slice] D[slice, :].  Items
+    // that read the same tile of A (same rows and slice, another column group)
+    // get indices 8 apart, so that they run on the same XCD (workgroups are
+    // dealt to the XCDs round robin) and share that tile in its L2.
+    const int tiles1 = mt1 * LS_SPLIT;
+    const int items1 = (tiles1 + 7) / 8 * 8 * nact;
     for (int q = rank; q < items1; q += G) {
-      const int sp = q % LS_SPLIT, rest = q / LS_SPLIT, mt = rest % mt1, gi = s_act[rest / mt1];
+      const int r8 = q >> 3, base = ((r8 / nact) << 3) + (q & 7);
+      if (base >= tiles1) continue;
+      const int gi = s_act[r8 % nact], sp = base % LS_SPLIT, mt = base / LS_SPLIT;
       const long k0 = sp * kslice, k1 = (k0 + kslice) < n ? (k0 + kslice) : n;
-      double4_t acc[2];
+      double4_t acc[4];
       gemm_item(gs, a.A, n, 0, (long)mt * LS_TM, m, a.D, n, (long)gi * LS_TN, B, k0, k1, acc);
       gemm_store(a.Yp + sp * ystride, m, (long)mt * LS_TM, m, (long)gi * LS_TN, B, acc);
     }
@@ -640,11 +658,14 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm_lockstep(LArgs a) {
       }
     }
     if ((aborted = team_barrier(t))) break;
-    // second product: T = A^T Y
-    const int items2 = nact * mt2;
+    // second product: T = A^T Y (same XCD grouping of the items sharing a
+    // column block of A)
+    const int items2 = (mt2 + 7) / 8 * 8 * nact;
     for (int q = rank; q < items2; q += G) {
-      const int ct = q % mt2, gi = s_act[q / mt2];
-      double4_t acc[2];
+      const int r8 = q >> 3, ct = ((r8 / nact) << 3) + (q & 7);
+      if (ct >= mt2) continue;
+      const int gi = s_act[r8 % nact];
+      double4_t acc[4];
       gemm_item(gs, a.A, n, 1, (long)ct * LS_TM, n, a.Y, m, (long)gi * LS_TN, B, 0, m, acc);
       gemm_store(a.T, n, (long)ct * LS_TM, n, (long)gi * LS_TN, B, acc);
     }

@@ -441,31 +441,42 @@ struct OpPdct {
       const int wpr = N2 >> 1;  // 32-bit words per row
       for (int i = threadIdx.x; i < 2 * wpr; i += MF_THREADS) ml[i] = i < wpr ? ga[i] : gb[i - wpr];
     }
-    for (int u2 = threadIdx.x; u2 < 2 * N2; u2 += MF_THREADS) {
-      const int s = u2 >= N2;
-      const int u = u2 - s * N2;
-      const int q = u >> lcb, c = u & ((1 << lcb) - 1);
-      const int j2 = col_j2(q, c);
-      const int k1 = s ? k1b : k1a;
-      const int gi = (((q << l1) + k1) << lcb) + c;
-      cplx v;
-      if (mode_in >= PB_RESID_STEP) {
-        const cplx a = Yx[gi], d = Yd[gi];
-        v = mkc(a.x + beta * d.x, a.y + beta * d.y);
-        if (mode_in == PB_RESID_STEP) Yx[gi] = v;
-      } else {
-        v = Y1[gi];
-        if (mode == PB_HAPPLY) {
-          if (!first) {
-            const cplx w = Y1p[gi];
-            v = mkc(v.x + beta * w.x, v.y + beta * w.y);
+    // The thread's loads (up to four elements at a time) are issued before
+    // its stores (the rows and the stored combination are different
+    // buffers), so that their latencies overlap.
+    {
+      constexpr int EB = 4;
+      const bool lin = mode_in >= PB_RESID_STEP;
+      const bool comb = lin || (mode == PB_HAPPLY && !first);
+      for (int e0 = 0; e0 < 2 * N2; e0 += EB * MF_THREADS) {
+        cplx va[EB], vb[EB];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+          const int u2 = e0 + threadIdx.x + e * MF_THREADS;
+          if (u2 < 2 * N2) {
+            const int s = u2 >= N2;
+            const int u = u2 - s * N2;
+            const int gi = ((((u >> lcb) << l1) + (s ? k1b : k1a)) << lcb) + (u & ((1 << lcb) - 1));
+            va[e] = lin ? Yx[gi] : Y1[gi];
+            if (comb) vb[e] = lin ? Yd[gi] : Y1p[gi];
           }
-          Y1p[gi] = v;
-        } else if (mode == PB_RESID) {
-          Yx[gi] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+          const int u2 = e0 + threadIdx.x + e * MF_THREADS;
+          if (u2 < 2 * N2) {
+            const int s = u2 >= N2;
+            const int u = u2 - s * N2;
+            const int q = u >> lcb, c = u & ((1 << lcb) - 1);
+            const int gi = (((q << l1) + (s ? k1b : k1a)) << lcb) + c;
+            cplx v = va[e];
+            if (comb) v = mkc(v.x + beta * vb[e].x, v.y + beta * vb[e].y);
+            if (mode_in == PB_RESID_STEP || (!lin && mode == PB_RESID)) Yx[gi] = v;
+            else if (!lin && mode == PB_HAPPLY) Y1p[gi] = v;
+            tile[s * N2 + col_j2(q, c)] = v;
+          }
         }
       }
-      tile[s * N2 + j2] = v;
     }
     __syncthreads();
     lds_fft(tile, l2, 1, 0, l2, -1, tw, log2M());

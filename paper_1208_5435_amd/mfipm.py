@@ -182,10 +182,10 @@ class Solver:
             self.h = None
             self._ws = None
 
-    def __del__(self):
-        # At interpreter shutdown the runtime may already be gone; the exit
-        # handler above has closed every handle by then.
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # At interpreter shutdown the runtime may already be gone (and module
+        # globals cleared); the exit handler above has closed every handle.
+        if _finalizing():
             return
         try:
             self.close()
