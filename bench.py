@@ -14,7 +14,11 @@ tau_i = 1e-2 ||A_i^T b_i||_inf; `value` is solves per second of that batch.
 Workloads: batched_dense (default), pdct_hdr (partial DCT n = 2^20),
 grad (32 signals sharing a partial DCT, n = 2^18, forward + adjoint),
 shared_dense (256 signals sharing one 2048 x 8192 dense A, FP64 MFMA),
-pdct (partial DCT n = 2^16), dense (256 x 1024).
+phase (a phase-transition sweep of small partial-DCT instances),
+pdct (partial DCT n = 2^16), dense (256 x 1024), wht / wht_hdr (partial
+Walsh-Hadamard n = 2^16 / 2^20, with the recipes of pdct / pdct_hdr),
+direct (exact Newton directions by Cholesky, n = 4096, with the n = 2^5 ..
+2^12 sweep of both variants).
 
 Roofline: algorithmic bytes (or flops) of the timed launch divided by its
 duration measured with HIP events on the library's stream (average over the
@@ -49,7 +53,7 @@ METRIC = "l1-LS solves/sec + PCG matvec HBM GB/s (% peak), batched & grad vs pla
 
 
 def alg_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
-    op = 16.0 * (n + m) if kind == "pdct" else 8.0 * m * n
+    op = 16.0 * (n + m) if kind in ("pdct", "wht") else 8.0 * m * n
     vec = 56.0 * n if reduced else 112.0 * n  # reduced: x, r, p, Theta_bar^{-1} are n-vectors
     pcg = info["pcg_iters"] * (vec + op)
     ipm = (info["ipm_iters"] + info["correctors"] + 1) * (160.0 * n + op)
@@ -57,7 +61,7 @@ def alg_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> f
 
 
 def adjoint_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
-    op = 16.0 * (n + m) if kind == "pdct" else 8.0 * m * n
+    op = 16.0 * (n + m) if kind in ("pdct", "wht") else 8.0 * m * n
     vec = 56.0 * n if reduced else 112.0 * n
     return info["pcg_iters"] * (vec + op) + 2 * (160.0 * n + op)
 
@@ -168,7 +172,12 @@ def cpu_baseline_single(kind, inst, budget_s):
     to one thread; scipy.fft single worker), as many as fit in the budget."""
     from threadpoolctl import threadpool_limits
     from oracle import mfipm_ref as R
-    op = R.DenseOperator(inst.A) if kind == "dense" else R.PartialDCTOperator(inst.n, inst.rows)
+    if kind == "dense":
+        op = R.DenseOperator(inst.A)
+    elif kind == "wht":
+        op = R.PartialWHTOperator(inst.n, inst.rows)
+    else:
+        op = R.PartialDCTOperator(inst.n, inst.rows)
     times = []
     with threadpool_limits(1):
         t_end = time.perf_counter() + budget_s
@@ -226,6 +235,38 @@ def cpu_baseline_grad(n, batch, signals):
                       f"{np.mean([r[1] for r in res]):.1f} s per signal"}
 
 
+def cpu_baseline_phase(grid, stride):
+    """Every `stride`-th instance of the sweep through the oracle in worker
+    processes; the rate is scaled to the whole sweep by the instance count."""
+    from oracle import pool
+    sample = [g[3] for g in grid[::stride]]
+    cores = min(pool.host_cores(), len(sample))
+    with pool.executor(cores) as ex:
+        pool.warm(ex, cores)
+        t0 = time.perf_counter()
+        res = list(ex.map(pool.time_phase_instance, sample))
+        wall = time.perf_counter() - t0
+    return {"value": round(len(sample) / wall, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "host": pool.host_model(),
+            "sample": f"{len(sample)} of {len(grid)} instances (every {stride}th), {cores} worker processes, "
+                      f"{wall:.1f} s wall, {np.mean(res):.2f} s per solve"}
+
+
+def cpu_baseline_direct(n):
+    """One oracle direct-variant solve of the same instance (Cholesky of the
+    explicit 2n system by LAPACK), BLAS on all usable host cores, in a worker
+    process."""
+    from oracle import pool
+    cores = pool.host_cores()
+    with pool.executor(1) as ex:
+        pool.warm(ex, 1)
+        sec, its, status = ex.submit(pool.time_direct, n, cores).result()
+    return {"value": round(1.0 / sec, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "host": pool.host_model(),
+            "sample": f"1 full oracle direct solve of the same instance ({its} IPM iterations, {sec:.1f} s, "
+                      f"BLAS on {cores} threads)"}
+
+
 def cpu_baseline_shared_dense(batch, signals):
     from oracle import pool
     cores = min(pool.host_cores(), signals)
@@ -251,6 +292,12 @@ def make_single(name: str):
     if name == "pdct_hdr":
         inst = W.config_pdct_hdr()
         return "pdct", inst, f"pdct_hdr_n{inst.n}_m{inst.m}_k{inst.n // 200}"
+    if name == "wht":
+        inst = W.config_wht()
+        return "wht", inst, f"wht_n{inst.n}_m{inst.m}_k{inst.n // 100}"
+    if name == "wht_hdr":
+        inst = W.config_wht_hdr()
+        return "wht", inst, f"wht_hdr_n{inst.n}_m{inst.m}_k{inst.n // 200}"
     if name == "dense":
         inst = W.config_dense_256x1024()
         return "dense", inst, "dense_256x1024_k20"
@@ -270,7 +317,7 @@ def bench_single(args, torch, Solver):
             call = lambda: solver.solve(b, inst.tau, A=A)  # noqa: E731
         else:
             rows = torch.from_numpy(inst.rows).to(dev)
-            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n)  # noqa: E731
+            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n, transform=inst.transform)  # noqa: E731
         _calibration_copy(args, torch, dev)
         wall, kms, r = _timed(call, args, torch)
     finally:
@@ -284,7 +331,7 @@ def bench_single(args, torch, Solver):
            "ipm_iters": info["ipm_iters"], "pcg_iters": info["pcg_iters"], "correctors": info["correctors"],
            "nmat": info["nmat"], "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
            "kernel_ms_min": round(float(np.min(kms)), 4)}
-    kern = "k_mfipm<OpPdct,0>" if kind == "pdct" else "k_mfipm<OpDense,0>"
+    kern = {"pdct": "k_mfipm<OpPdct,0>", "wht": "k_mfipm<OpWht,0>", "dense": "k_mfipm<OpDense,0>"}[kind]
     out = _line(round(args.steps / wall, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
                 _hbm_roofline(alg_bytes(kind, n, m, info, args.reduced), kms_mean, kern, wl))
     if not args.no_cpu_baseline:
@@ -484,6 +531,116 @@ def bench_shared_dense(args, torch, Solver):
     return out
 
 
+def direct_flops(n: int, m: int, info: dict) -> float:
+    """Algorithmic flops of one direct-variant solve: K = A^T A once (its
+    lower half, m n^2), a Cholesky factorisation per IPM iteration (n^3 / 3),
+    two triangular sweeps per Newton direction (2 n^2), and the residuals'
+    products with A and A^T (2 m n each)."""
+    return (m * n * n + info["ipm_iters"] * n ** 3 / 3.0 + (info["ipm_iters"] + info["correctors"]) * 2.0 * n * n
+            + info["nmat"] * 2.0 * m * n)
+
+
+def bench_direct(args, torch, Solver):
+    """The direct-solver variant (Section 5.7): the Gaussian, noiseless,
+    tau = 1e-3 problem with n = 4096, m = 1024 solved with exact Newton
+    directions (Cholesky of the n x n system on FP64 MFMA), plus the paper's
+    size sweep n = 2^5 .. 2^12 with both variants (time and IPM iterations)."""
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    n = args.direct_n
+    inst = W.direct_scaling_instance(n)
+    m = inst.m
+    A = torch.from_numpy(inst.A).to(dev)
+    b = torch.from_numpy(inst.b).to(dev)
+    sd = Solver(device=dev, params={**_params(args), "direct": 1})
+    sp = Solver(device=dev, params=_params(args))
+    sweep = []
+    try:
+        run = lambda: sd.solve(b, inst.tau, A=A)  # noqa: E731
+        _calibration_copy(args, torch, dev)
+        wall, kms, r = _timed(run, args, torch)
+        if not args.no_plain:
+            for nn in W.DIRECT_SCALING_NS:
+                q = W.direct_scaling_instance(nn)
+                Aq = torch.from_numpy(q.A).to(dev)
+                bq = torch.from_numpy(q.b).to(dev)
+                row = {"n": nn, "m": q.m}
+                for name, s in (("direct", sd), ("pcg", sp)):
+                    s.solve(bq, q.tau, A=Aq)
+                    rr = s.solve(bq, q.tau, A=Aq)
+                    i = rr.infos[0]
+                    row[name] = {"ms": round(rr.kernel_ms, 3), "ipm_iters": i["ipm_iters"],
+                                 "pcg_iters": i["pcg_iters"], "status": i["status_name"]}
+                sweep.append(row)
+    finally:
+        sd.close()
+        sp.close()
+    info = r.infos[0]
+    if info["status"] != 0:
+        print(f"bench.py: direct solve did not converge: {info}", file=sys.stderr)
+    kms_mean = float(np.mean(kms))
+    flops = direct_flops(n, m, info)
+    achieved = flops / (kms_mean * 1e-3) / 1e12
+    wl = f"direct_n{n}_m{m}"
+    cfg = {"workload": wl, "n": n, "m": m, "tau": inst.tau, "tol": 1e-8, "direct": 1,
+           "ipm_iters": info["ipm_iters"], "correctors": info["correctors"], "rel_gap": info["rel_gap"],
+           "kernel_ms_mean": round(kms_mean, 3), "sweep_n_2e5_to_2e12": sweep}
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": counter_traffic(wl),
+            "kernel": "k_mfipm<OpDenseDirect,0>", "alg_flops_per_launch": flops}
+    out = _line(round(args.steps / wall, 3), "solves/s", args, 1e3 * wall / args.steps, cfg, roof)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_direct(n)
+    return out
+
+
+def bench_phase(args, torch, Solver):
+    """The average phase-transition sweep (noiseless partial DCT, n = 1024,
+    delta = m/n in 0.1..0.9, rho = k/m in 0.05..0.95, +-1 spikes) as one
+    batched launch of many small instances, each with its own rows."""
+    import workloads as W
+    grid = W.phase_transition_grid(trials=args.phase_trials)
+    insts = [g[3] for g in grid]
+    B, n = len(insts), insts[0].n
+    dev = torch.device("cuda", 0)
+    n_off = np.arange(B + 1, dtype=np.int64) * n
+    m_off = np.concatenate([[0], np.cumsum([i.m for i in insts])]).astype(np.int64)
+    rows = torch.from_numpy(np.concatenate([i.rows for i in insts])).to(dev)
+    b = torch.from_numpy(np.concatenate([i.b for i in insts])).to(dev)
+    taus = np.array([i.tau for i in insts])
+    solver = Solver(device=dev, params={**W.PHASE_PARAMS, **_params(args)})
+    try:
+        solver.set_launch(args.workgroups, args.team, args.tile)
+        run = lambda: solver.solve_batched(b, taus, n_off, m_off, rows=rows)  # noqa: E731
+        _calibration_copy(args, torch, dev)
+        wall, kms, r = _timed(run, args, torch)
+    finally:
+        solver.close()
+    x = r.x.cpu().numpy().reshape(B, n)
+    re = [float(np.linalg.norm(x[j] - insts[j].x_true) / np.linalg.norm(insts[j].x_true)) for j in range(B)]
+    rate = {}
+    for (d, rho, _, _), e in zip(grid, re):
+        rate.setdefault(d, {}).setdefault(rho, []).append(e <= 1e-5)
+    transition = {str(d): max([rho for rho, v in sorted(rs.items()) if np.mean(v) >= 0.5], default=0.0)
+                  for d, rs in rate.items()}
+    infos = r.infos
+    kms_mean = float(np.mean(kms))
+    ab = sum(alg_bytes("pdct", n, insts[j].m, infos[j], args.reduced) for j in range(B))
+    value = B * args.steps / wall
+    wl = f"phase_transition_pdct_n{n}_{B}"
+    statuses = {}
+    for i in infos:
+        statuses[i["status_name"]] = statuses.get(i["status_name"], 0) + 1
+    cfg = {"workload": wl, "batch": B, "n": n, "trials": args.phase_trials, "tol": W.PHASE_PARAMS["tol"],
+           "tolpcg": W.PHASE_PARAMS["tolpcg"], "c_tau": W.PHASE_C_TAU, "kernel_ms_mean": round(kms_mean, 3),
+           "statuses": statuses, "rho_50pct_by_delta": transition}
+    out = _line(round(value, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
+                _hbm_roofline(ab, kms_mean, "k_mfipm<OpPdct,0>", wl))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_phase(grid, stride=20)
+    return out
+
+
 def tune_workload(args, torch, Solver):
     """Autotunes the launch shape of one workload (forward, and backward for
     the gradient batch) and writes it to the package's shipped table."""
@@ -492,7 +649,7 @@ def tune_workload(args, torch, Solver):
     solver = Solver(device=dev, params=_params(args))
     out = args.tune_out or autotune.SHIPPED
     jobs = []
-    if args.workload in ("pdct", "pdct_hdr", "dense"):
+    if args.workload in ("pdct", "pdct_hdr", "wht", "wht_hdr", "dense"):
         kind, inst, _ = make_single(args.workload)
         b = torch.from_numpy(inst.b).to(dev)
         if kind == "dense":
@@ -501,8 +658,8 @@ def tune_workload(args, torch, Solver):
             op = 0
         else:
             rows = torch.from_numpy(inst.rows).to(dev)
-            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n)  # noqa: E731
-            op = 1
+            call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n, transform=inst.transform)  # noqa: E731
+            op = 2 if kind == "wht" else 1
         jobs.append((solver.tune_key(op, inst.n, inst.m, 1, True), call,
                      autotune.candidates(op, inst.n, inst.m, 1, solver.num_cu)))
     elif args.workload == "grad":
@@ -528,7 +685,7 @@ def tune_workload(args, torch, Solver):
         jobs.append((solver.tune_key(0, nmax, mmax, len(insts), False), call,
                      autotune.candidates(0, nmax, mmax, len(insts), solver.num_cu)))
     else:
-        raise SystemExit("--tune supports pdct, pdct_hdr, dense, batched_dense, grad")
+        raise SystemExit("--tune supports pdct, pdct_hdr, wht, wht_hdr, dense, batched_dense, grad")
     try:
         for key, call, cands in jobs:
             best, ms, table = autotune.tune(solver, call, key, cands, reps=3, path=out, verbose=True)
@@ -544,9 +701,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched_dense",
-                    choices=["batched_dense", "pdct_hdr", "grad", "shared_dense", "pdct", "dense"])
+                    choices=["batched_dense", "pdct_hdr", "grad", "shared_dense", "phase", "pdct", "dense", "wht",
+                             "wht_hdr", "direct"])
+    ap.add_argument("--direct-n", type=int, default=4096, help="n of the direct workload (m = n/4)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--grad-n", type=int, default=1 << 18)
+    ap.add_argument("--phase-trials", type=int, default=10)
     ap.add_argument("--team", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -586,8 +746,8 @@ def main():
     if args.tune:
         tune_workload(args, torch, Solver)
         return
-    fn = {"batched_dense": bench_batched_dense, "grad": bench_grad,
-          "shared_dense": bench_shared_dense}.get(args.workload, bench_single)
+    fn = {"batched_dense": bench_batched_dense, "grad": bench_grad, "shared_dense": bench_shared_dense,
+          "phase": bench_phase, "direct": bench_direct}.get(args.workload, bench_single)
     out = fn(args, torch, Solver)
     print(json.dumps(out), flush=True)
 

@@ -77,6 +77,9 @@ extern "C" {
 #define MFIPM_OP_DENSE 0 /* explicit m x n row-major matrix                                     */
 #define MFIPM_OP_PDCT 1  /* rows of the orthonormal DCT-II of length n (Section 2, eq.
                             (eq:orthonormality): A A^T = I); n a power of two, 64 <= n <= 2^20 */
+#define MFIPM_OP_WHT 2   /* rows of the orthonormal Walsh-Hadamard matrix H_n / sqrt(n) in
+                            natural (Sylvester) order, another fast transform with orthonormal
+                            rows (Section 1, Section 2); n a power of two, 64 <= n <= 2^20   */
 
 typedef struct mfipm_handle mfipm_handle;
 
@@ -84,7 +87,9 @@ typedef struct mfipm_handle mfipm_handle;
  * DENSE: A is row-major m x n with leading dimension lda >= n (borrowed).
  * PDCT : rows holds m sorted, distinct indices in [0, n) of the DCT-II rows
  *        kept by A (borrowed); A*d = DCT-II_ortho(d)[rows],
- *        A^T*y = DCT-III_ortho(zero-fill(y)).                                  */
+ *        A^T*y = DCT-III_ortho(zero-fill(y)).
+ * WHT  : rows as for PDCT, of W = H_n / sqrt(n); A*d = (W d)[rows],
+ *        A^T*y = W zero-fill(y).                                                */
 typedef struct {
   int32_t op;
   int64_t m, n;
@@ -125,6 +130,19 @@ typedef struct {
                             the vector traffic per PCG iteration; different PCG
                             iterates).  Lock-step batches use the 2n system and
                             are not taken when this is set.                     */
+  int32_t direct;        /* 0: PCG (the matrix-free method);
+                            1: exact Newton directions by a direct solver
+                            (Section 5.7): Cholesky factorisation of the
+                            n x n system above, M = Theta_bar^{-1} + A^T A,
+                            formed from A^T A (computed once per solve) at
+                            every IPM iteration, the corrector reusing the
+                            factor.  Forward solves with a DENSE operator and
+                            n <= 8192 only (else MFIPM_ERR_INVALID_ARG); the
+                            workspace grows by about 16 n^2 bytes per
+                            concurrently solved instance; pcg_iters reports 0;
+                            mfipm_backward ignores it (adjoint by PCG).  A
+                            factorisation that meets a non-positive pivot
+                            ends the solve with MFIPM_STATUS_PCG_BREAKDOWN.   */
 } mfipm_params;
 
 /* Per-instance report (HOST memory). */

@@ -82,6 +82,7 @@ class Params:
     mxiterpcg_adj: int = 1000
     step_min: float = 1e-14   # both step sizes below this -> STEP_UNDERFLOW
     reduced: int = 0          # 1: PCG on the n x n system of the Theorem (see pcg_reduced)
+    direct: int = 0           # 1: exact Newton directions by Cholesky (Section 5.7; see direct_solve)
 
 
 # --- operators ----------------------------------------------------------------
@@ -136,6 +137,50 @@ class PartialDCTOperator:
         j = np.arange(n)[None, :].astype(np.float64)
         alpha = np.where(k == 0, math.sqrt(1.0 / n), math.sqrt(2.0 / n))
         return alpha * np.cos(math.pi * (2.0 * j + 1.0) * k / (2.0 * n))
+
+
+def fwht(x: np.ndarray) -> np.ndarray:
+    """Unnormalised Walsh-Hadamard transform in natural (Sylvester) order:
+    H_1 = [1], H_2n = [[H_n, H_n], [H_n, -H_n]], applied by the recursive
+    definition (pairs at distance h combined as (a + b, a - b) for
+    h = 1, 2, 4, ...)."""
+    y = np.array(x, dtype=np.float64, copy=True)
+    n = y.shape[0]
+    h = 1
+    while h < n:
+        y = y.reshape(-1, 2, h)
+        a = y[:, 0, :].copy()
+        b = y[:, 1, :]
+        y = np.stack([a + b, a - b], axis=1).reshape(n)
+        h *= 2
+    return y
+
+
+class PartialWHTOperator:
+    """A = R_m W: rows `rows` of the orthonormal Walsh-Hadamard matrix
+    W = H_n / sqrt(n) (natural order; n a power of two), one of the fast
+    partial transforms the paper names beside the DCT.  W is symmetric and
+    orthogonal, so A^T y = W (zero-fill of y) and A A^T = I."""
+
+    def __init__(self, n: int, rows: np.ndarray):
+        self.n = int(n)
+        self.rows = np.asarray(rows, dtype=np.int64)
+        self.m = int(self.rows.shape[0])
+
+    def matvec(self, x):
+        return fwht(x)[self.rows] / math.sqrt(self.n)
+
+    def rmatvec(self, y):
+        full = np.zeros(self.n)
+        full[self.rows] = y
+        return fwht(full) / math.sqrt(self.n)
+
+    def frob2(self) -> float:
+        return float(self.m)
+
+    def dense(self) -> np.ndarray:
+        """Explicit rows from Sylvester's construction (small n only)."""
+        return scipy.linalg.hadamard(self.n)[self.rows] / math.sqrt(self.n)
 
 
 def make_operator(A=None, n=None, rows=None):
@@ -382,7 +427,7 @@ def solve(op, b, tau, params: Params | None = None, linsolve: str = "pcg",
     mu = float(z @ s) / (2 * n)
 
     def lin(theta_inv, rhs):
-        if linsolve == "direct":
+        if linsolve == "direct" or p.direct:
             return direct_solve(op, theta_inv, rhs)
         if p.reduced:
             return pcg_reduced(op, theta_inv, rho, rhs, p.tolpcg, p.mxiterpcg)

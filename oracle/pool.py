@@ -110,3 +110,26 @@ def time_grad_signal(j: int, n: int, batch: int):
     t1 = time.perf_counter()
     R.backward(op, r.z, r.s, r.x - inst.x_true[j])
     return t1 - t0, time.perf_counter() - t1, r.ipm_iters, r.status
+
+
+def time_phase_instance(inst):
+    """One instance of the phase-transition sweep: oracle solve time."""
+    import workloads as W
+    from oracle import mfipm_ref as R
+    t0 = time.perf_counter()
+    R.solve(R.PartialDCTOperator(inst.n, inst.rows), inst.b, inst.tau, R.Params(**W.PHASE_PARAMS))
+    return time.perf_counter() - t0
+
+
+def time_direct(n: int, threads: int):
+    """Draws the Section 5.7 problem of length n and solves it with the
+    oracle's direct variant (Cholesky of the explicit 2n system), BLAS on
+    `threads` threads.  Returns (solve s, IPM iterations, status)."""
+    from threadpoolctl import threadpool_limits
+    import workloads as W
+    from oracle import mfipm_ref as R
+    inst = W.direct_scaling_instance(n)
+    with threadpool_limits(threads):
+        t0 = time.perf_counter()
+        r = R.solve(R.DenseOperator(inst.A), inst.b, inst.tau, R.Params(direct=1))
+        return time.perf_counter() - t0, r.ipm_iters, r.status

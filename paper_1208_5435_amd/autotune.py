@@ -91,6 +91,13 @@ def candidates(op_kind: int, n_max: int, m_max: int, batch: int, num_cu: int = 2
             for wg in (0, 32, 64, 96, 128, 192, 256):
                 for t in tiles:
                     out.append((wg, 0, t))
+        elif op_kind == 2:  # partial Walsh-Hadamard: log2 of the column length
+            ln = int(math.log2(n_max))
+            base = ln // 2
+            tiles = sorted({t for t in (base - 1, base, base + 1) if 2 <= t <= min(13, ln - 2) and ln - t <= 12})
+            for wg in (0, 32, 64, 128, 192, 256):
+                for t in tiles:
+                    out.append((wg, 0, t))
         else:
             for wg in (0, 16, 32, 64, 128, 256):
                 out.append((wg, 0, 0))

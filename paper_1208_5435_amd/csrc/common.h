@@ -133,28 +133,38 @@ __device__ __forceinline__ int spin_ge(unsigned long long* p, unsigned long long
 
 // One-time set-up of the barrier groups: every workgroup registers its XCD,
 // waits for the whole team, then reads its group's size and the number of
-// groups.  Returns nonzero if the run was aborted.
+// groups.  The workgroup's rank is then renumbered XCD by XCD (the groups in
+// XCD order, each in registration order), so that consecutive work items,
+// which touch neighbouring memory, run on workgroups sharing one L2.  Every
+// pass keeps its partial sums per item, so results do not depend on this
+// numbering.  Returns nonzero if the run was aborted.
 __device__ __forceinline__ int team_init(Team& t) {
-  __shared__ int s_init[3];
+  __shared__ int s_init[4];
   t.gen = 0;
   t.xcd = hw_xcd_id();
   if (threadIdx.x == 0) {
     unsigned long long* reg = t.ctl + MF_CTL_REG_WORD;
-    __hip_atomic_fetch_add(reg + t.xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long pos =
+        __hip_atomic_fetch_add(reg + t.xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_s_waitcnt(0);
     __hip_atomic_fetch_add(reg + MF_MAX_XCD, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ab = spin_ge(reg + MF_MAX_XCD, (unsigned long long)t.size, t);
-    int ng = 0;
-    for (int x = 0; x < MF_MAX_XCD; ++x)
-      ng += __hip_atomic_load(reg + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
+    int ng = 0, before = 0;
+    for (int x = 0; x < MF_MAX_XCD; ++x) {
+      const int c = (int)__hip_atomic_load(reg + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ng += c > 0;
+      if (x < t.xcd) before += c;
+    }
     s_init[0] = ab;
     s_init[1] = (int)__hip_atomic_load(reg + t.xcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s_init[2] = ng;
+    s_init[3] = before + (int)pos;
   }
   __syncthreads();
   const int ab = s_init[0];
   t.gsize = s_init[1];
   t.ngroups = s_init[2];
+  if (!ab) t.rank = s_init[3];
   __syncthreads();
   return ab;
 }
@@ -187,6 +197,12 @@ __device__ __forceinline__ int team_barrier(Team& t) {
   __syncthreads();
   return s_abort;
 }
+
+// A workgroup's view of its team during one instance.
+struct Ctx {
+  Team t;
+  double* red;  // LDS reduction scratch (MF_RED_DOUBLES doubles)
+};
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  kind: 0 = sum, 1 = max, 2 = min.

@@ -10,9 +10,13 @@
 // all workgroups of a team hold bit-identical scalars and take identical
 // branch decisions.
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "op_dense.h"
 #include "op_pdct.h"
+#include "op_wht.h"
+#include "direct.h"
 
 // mirror of mfipm_params (host struct) -- same field order and types
 struct DevParams {
@@ -29,6 +33,7 @@ struct DevParams {
   int32_t mxiterpcg_adj;
   double step_min;
   int32_t reduced;
+  int32_t direct;
 };
 
 struct DevInfo {
@@ -51,6 +56,7 @@ struct TeamWS {
   unsigned char* mask;
   double *bt, *XS;
   double *partA, *partB, *partC, *partS;
+  double *DK, *DM, *DLi, *DY;  // direct variant: A^T A, M / L, diagonal inverses, sweep vector
   unsigned long long* bar;
   int* slot;
   int* err;
@@ -58,7 +64,7 @@ struct TeamWS {
 
 struct TeamLayout {  // byte offsets inside one team region
   long X, R, P, TI, DZ, DS, Zs, Ss, D, Yv, PT, Dp0, Dp1, Dx0, Dx1, Dd, Y1, Y1p, Y2, Yx, Yd, mask, bt, XS, partA, partB,
-      partC, partS;
+      partC, partS, DK, DM, DLi, DY;
   int pt_chunks;  // dense fused path: capacity of PT in chunks
   long stride;
 };
@@ -123,6 +129,10 @@ __device__ __forceinline__ TeamWS make_ws(const KArgs& a, int team) {
   w.partB = (double*)(base + a.lay.partB);
   w.partC = (double*)(base + a.lay.partC);
   w.partS = (double*)(base + a.lay.partS);
+  w.DK = (double*)(base + a.lay.DK);
+  w.DM = (double*)(base + a.lay.DM);
+  w.DLi = (double*)(base + a.lay.DLi);
+  w.DY = (double*)(base + a.lay.DY);
   char* ctl = a.team_ctl + (long)team * MF_CTL_BYTES;
   w.bar = (unsigned long long*)ctl;
   w.slot = (int*)(ctl + MF_CTL_SLOT_BYTES);
@@ -555,10 +565,6 @@ struct FBwdGatherT {
 // ------------------------------------------------------------------------
 // pass runners
 // ------------------------------------------------------------------------
-struct Ctx {
-  Team t;
-  double* red;  // LDS reduction scratch (MF_RED_DOUBLES doubles)
-};
 
 template <int K>
 __device__ __forceinline__ void kinds_fill(int (&k)[K], int a, int b = 0, int c = 0, int d = 0) {
@@ -619,9 +625,9 @@ __device__ __forceinline__ void run_B<OpDense>(Ctx& cx, OpDense& op, int mode, d
   }
 }
 
-template <>
-__device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*, double beta,
-                                              int first) {
+// transform operators: per-thread partials reduced per item
+template <class OP>
+__device__ __forceinline__ void run_B_transform(Ctx& cx, OP& op, int mode, double* part, double beta, int first) {
   const int ni = op.nB();
   const int kinds[2] = {0, 0};
   for (int it = cx.t.rank; it < ni; it += cx.t.size) {
@@ -634,6 +640,21 @@ __device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, dou
     }
   }
 }
+template <>
+__device__ __forceinline__ void run_B<OpPdct>(Ctx& cx, OpPdct& op, int mode, double* part, double*, double beta,
+                                              int first) {
+  run_B_transform(cx, op, mode, part, beta, first);
+}
+template <>
+__device__ __forceinline__ void run_B<OpWht>(Ctx& cx, OpWht& op, int mode, double* part, double*, double beta,
+                                             int first) {
+  run_B_transform(cx, op, mode, part, beta, first);
+}
+template <>
+__device__ __forceinline__ void run_B<OpDenseDirect>(Ctx& cx, OpDenseDirect& op, int mode, double* part, double* out,
+                                                     double beta, int first) {
+  run_B<OpDense>(cx, op, mode, part, out, beta, first);
+}
 
 // the search-direction buffers of iteration `it` (dense: alternating d of p)
 __device__ __forceinline__ void op_direction(OpDense& op, const TeamWS& w, int it) {
@@ -641,11 +662,15 @@ __device__ __forceinline__ void op_direction(OpDense& op, const TeamWS& w, int i
   op.Dp_cur = (it & 1) ? w.Dp1 : w.Dp0;
 }
 __device__ __forceinline__ void op_direction(OpPdct&, const TeamWS&, int) {}
+__device__ __forceinline__ void op_direction(OpWht&, const TeamWS&, int) {}
 
 // The operator's first stage (pass A) writes the transform of the step
 // direction instead of the operator input (on = 1), or back (on = 0).
 __device__ __forceinline__ void op_step_target(OpDense& op, const TeamWS& w, int on) { op.D = on ? w.Dd : w.D; }
 __device__ __forceinline__ void op_step_target(OpPdct& op, const TeamWS& w, int on) { op.Y1 = on ? w.Yd : w.Y1; }
+__device__ __forceinline__ void op_step_target(OpWht& op, const TeamWS& w, int on) {
+  op.Y1 = reinterpret_cast<double*>(on ? w.Yd : w.Y1);
+}
 // After a residual pass B that kept x: dense swaps its current / next x.
 __device__ __forceinline__ void op_x_advance(OpDense& op) {
   double* t = op.Dxc;
@@ -653,6 +678,7 @@ __device__ __forceinline__ void op_x_advance(OpDense& op) {
   op.Dxn = t;
 }
 __device__ __forceinline__ void op_x_advance(OpPdct&) {}
+__device__ __forceinline__ void op_x_advance(OpWht&) {}
 
 // elementwise pass over [0, n), items of 1024 indices
 template <class F>
@@ -755,6 +781,22 @@ __device__ __forceinline__ void make_op(OpDense& op, const KArgs& a, const InstD
   op.nchunk = (int)((d.m + op.chunk_rows - 1) / op.chunk_rows);
 }
 
+// Direct variant: the dense operator for the residuals and steps, plus the
+// factorisation's buffers; its LDS staging reuses the dense passes' LDS
+// (nothing there outlives a pass).
+__device__ __forceinline__ void make_op(OpDenseDirect& op, const KArgs& a, const InstDesc& d, const TeamWS& w,
+                                        char* lds, int team_size) {
+  make_op(static_cast<OpDense&>(op), a, d, w, lds, team_size);
+  op.K = w.DK;
+  op.M = w.DM;
+  op.Li = w.DLi;
+  op.y = w.DY;
+  op.sX = reinterpret_cast<double*>(lds);
+  op.sY = op.sX + DC_NB * DC_LD;
+  op.npad = dc_npad(d.n);
+  op.T = (int)(op.npad / DC_NB);
+}
+
 __device__ __forceinline__ int ilog2(long v) {
   int l = 0;
   while ((1L << l) < v) ++l;
@@ -800,22 +842,56 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.a1 = sqrt(2.0 / (double)d.n);
 }
 
+__device__ __forceinline__ void make_op(OpWht& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds,
+                                        int team_size) {
+  op.n = d.n;
+  op.m = d.m;
+  const int ln = ilog2(d.n);
+  int l1 = ln / 2;
+  if (a.tile_param > 0) l1 = a.tile_param;
+  // columns of length <= 2^13 (the LDS tile), rows of length <= 2^12
+  if (l1 > 13) l1 = 13;
+  if (l1 > ln - 2) l1 = ln - 2;
+  if (l1 < 2) l1 = 2;
+  if (ln - l1 > 12) l1 = ln - 12;
+  op.l1 = l1;
+  op.l2 = ln - l1;
+  op.N1 = 1 << op.l1;
+  op.N2 = 1 << op.l2;
+  // widest blocks that fit the 8192-double tile, narrowed while they would
+  // leave workgroups of the team idle
+  int lcb = 4;
+  if (lcb > 13 - op.l1) lcb = 13 - op.l1;
+  if (lcb > op.l2) lcb = op.l2;
+  while (lcb > 0 && (op.N2 >> lcb) < team_size) --lcb;
+  int lrb = 3;
+  if (lrb > 13 - op.l2) lrb = 13 - op.l2;
+  if (lrb > op.l1) lrb = op.l1;
+  while (lrb > 0 && (op.N1 >> lrb) < team_size) --lrb;
+  op.lcb = lcb;
+  op.lrb = lrb;
+  op.rows = a.rows + (a.shared_op ? 0 : d.m_off);
+  op.b = a.b ? a.b + d.m_off : nullptr;
+  op.Y1 = reinterpret_cast<double*>(w.Y1);
+  op.Y1p = reinterpret_cast<double*>(w.Y1p);
+  op.Yx = reinterpret_cast<double*>(w.Yx);
+  op.Yd = reinterpret_cast<double*>(w.Yd);
+  op.Y2 = reinterpret_cast<double*>(w.Y2);
+  op.mask = w.mask;
+  op.bt = w.bt;
+  op.XS = w.XS;
+  op.tile = reinterpret_cast<double*>(lds);
+  op.scale = 1.0 / sqrt((double)d.n);
+}
+
 // Dense set-up: nothing to build.  Returns 0 (ok) or ST_ABORTED.
 __device__ __forceinline__ int op_setup(Ctx& cx, OpDense&, const KArgs&, const TeamWS&, int) { return 0; }
 
-// PDCT set-up: copy the twiddle tables to LDS, zero the spectral mask / b~,
-// then scatter the sampled rows (checking they are sorted, distinct and in
-// range).  with_b = 0 skips b~.
-__device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS& w, int with_b) {
-  {
-    cplx* lo = const_cast<cplx*>(op.tw.lo);
-    cplx* hi = const_cast<cplx*>(op.tw.hi);
-    const int nlo = 1 << a.tw_lo_bits;
-    const int nhi = 1 << (a.tw_log2n_max + 2 - a.tw_lo_bits);
-    for (int e = threadIdx.x; e < nlo; e += MF_THREADS) lo[e] = a.tw_lo[e];
-    for (int e = threadIdx.x; e < nhi; e += MF_THREADS) hi[e] = a.tw_hi[e];
-    __syncthreads();
-  }
+// Transform operators' set-up: zero the coefficient mask / b~, then scatter
+// the sampled rows (checking they are sorted, distinct and in range).
+// with_b = 0 skips b~.
+template <class OP>
+__device__ __forceinline__ int rows_setup(Ctx& cx, OP& op, const TeamWS& w, int with_b) {
   const long n = op.n;
   const long nthr = (long)cx.t.size * MF_THREADS;
   const long gt = (long)cx.t.rank * MF_THREADS + threadIdx.x;
@@ -842,6 +918,21 @@ __device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, con
   return 0;
 }
 
+// PDCT set-up: the twiddle tables to LDS, then the rows.
+__device__ __forceinline__ int op_setup(Ctx& cx, OpPdct& op, const KArgs& a, const TeamWS& w, int with_b) {
+  cplx* lo = const_cast<cplx*>(op.tw.lo);
+  cplx* hi = const_cast<cplx*>(op.tw.hi);
+  const int nlo = 1 << a.tw_lo_bits;
+  const int nhi = 1 << (a.tw_log2n_max + 2 - a.tw_lo_bits);
+  for (int e = threadIdx.x; e < nlo; e += MF_THREADS) lo[e] = a.tw_lo[e];
+  for (int e = threadIdx.x; e < nhi; e += MF_THREADS) hi[e] = a.tw_hi[e];
+  __syncthreads();
+  return rows_setup(cx, op, w, with_b);
+}
+__device__ __forceinline__ int op_setup(Ctx& cx, OpWht& op, const KArgs&, const TeamWS& w, int with_b) {
+  return rows_setup(cx, op, w, with_b);
+}
+
 // rho: Frobenius-closest scalar to A^T A (Section 4, before eq. (eq:ne2_P)).
 __device__ __forceinline__ double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, int& ab) {
   const int ni = op.nF();
@@ -856,6 +947,10 @@ __device__ __forceinline__ double op_rho(Ctx& cx, OpDense& op, const TeamWS& w, 
   return r[0] / (double)op.n;
 }
 __device__ __forceinline__ double op_rho(Ctx&, OpPdct& op, const TeamWS&, int& ab) {
+  ab = 0;
+  return (double)op.m / (double)op.n;  // orthonormal rows: ||A||_F^2 = m
+}
+__device__ __forceinline__ double op_rho(Ctx&, OpWht& op, const TeamWS&, int& ab) {
   ab = 0;
   return (double)op.m / (double)op.n;  // orthonormal rows: ||A||_F^2 = m
 }
@@ -1056,6 +1151,13 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
     rho = op_rho(cx, op, w, ab);
     if (ab) st = status = ST_ABORTED;
   }
+  constexpr bool DIRECT = std::is_same<OP, OpDenseDirect>::value;
+  if constexpr (DIRECT) {
+    if (!st) {
+      st = direct_setup(cx, op, w.err);
+      if (st) status = st;
+    }
+  }
   if (!st) {
     double aP_prev = 1.0, aD_prev = 1.0, aP = 0.0, aD = 0.0;
     int mode = RA_INIT;
@@ -1088,7 +1190,13 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
         break;
       }
       int its = 0;
-      st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, ro.yty, &its);
+      if constexpr (DIRECT) {
+        // exact direction: factorise M for this Theta, then the two sweeps
+        st = direct_factor(cx, op, red_vec(w, n).TB, w.err);
+        if (!st) st = direct_solve(cx, op, red_vec(w, n).R);
+      } else {
+        st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, ro.rhs2, ro.rty, ro.yty, &its);
+      }
       pcg_total += its;
       nmat += 2 * its;
       if (st) {
@@ -1100,7 +1208,8 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
       fs.S = S;
       fs.TI = w.TI;
       fs.X = RED ? w.R : w.X;
-      fs.Xr = red_vec(w, n).X;
+      if constexpr (DIRECT) fs.Xr = op.y;
+      else fs.Xr = red_vec(w, n).X;
       fs.DZ = w.DZ;
       fs.DS = w.DS;
       fs.sigma = sigma;
@@ -1126,7 +1235,8 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
           status = rc.status;
           break;
         }
-        st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, rc.yty, &its);
+        if constexpr (DIRECT) st = direct_solve(cx, op, red_vec(w, n).R);  // same factorisation
+        else st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg, prm.mxiterpcg, rc.rhs2, rc.rty, rc.yty, &its);
         pcg_total += its;
         nmat += 2 * its;
         if (st) {
@@ -1192,10 +1302,20 @@ __device__ __forceinline__ void op_forward_gather(Ctx&, OpDense&, const TeamWS&,
 __device__ __forceinline__ void op_forward_out(Ctx& cx, OpPdct& op, const TeamWS& w, double*) {
   run_B<OpPdct>(cx, op, PB_FWDOUT, w.partB, nullptr);
 }
-__device__ __forceinline__ void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, double* out) {
+template <class OP>
+__device__ __forceinline__ void forward_gather_rows(Ctx& cx, OP& op, const TeamWS& w, double* out) {
   const long nthr = (long)cx.t.size * MF_THREADS;
   for (long i = (long)cx.t.rank * MF_THREADS + threadIdx.x; i < op.m; i += nthr)
     out[i] = w.XS[op.coef_pos(op.rows[i])];
+}
+__device__ __forceinline__ void op_forward_gather(Ctx& cx, OpPdct& op, const TeamWS& w, double* out) {
+  forward_gather_rows(cx, op, w, out);
+}
+__device__ __forceinline__ void op_forward_out(Ctx& cx, OpWht& op, const TeamWS& w, double*) {
+  run_B<OpWht>(cx, op, WB_FWDOUT, w.partB, nullptr);
+}
+__device__ __forceinline__ void op_forward_gather(Ctx& cx, OpWht& op, const TeamWS& w, double* out) {
+  forward_gather_rows(cx, op, w, out);
 }
 
 // Adjoint: (Theta^{-1} + F F^T) w = [g; -g] at the stored state, then

@@ -23,6 +23,7 @@
 
 static_assert(sizeof(DevParams) == sizeof(mfipm_params), "params mirror");
 static_assert(sizeof(DevInfo) == sizeof(mfipm_info), "info mirror");
+static_assert(DC_LDS_BYTES <= (size_t)DN_FUSED_MAXN * sizeof(double2), "direct staging fits the dense LDS");
 
 // ------------------------------------------------------------------------
 // kernels
@@ -53,7 +54,7 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
     const int q = ld_flag(w.slot);
     if (q >= a.batch) break;
     const int ii = a.order[q];
-    if (BWD) backward_instance<OP, RED>(cx, a, ii, lds_dyn);
+    if constexpr (BWD) backward_instance<OP, RED>(cx, a, ii, lds_dyn);
     else solve_instance<OP, RED>(cx, a, ii, lds_dyn);
   }
 }
@@ -91,9 +92,9 @@ struct mfipm_handle {
   int req_wg, req_team, req_tile;
   hipEvent_t ev0, ev1;
   double last_ms;
-  int occ[2][2][2];          // [op][bwd][reduced] max resident workgroups per CU
+  int occ[4][2][2];          // [kernel kind][bwd][reduced] max resident workgroups per CU
   int occ_ls;                // the same for the lock-step kernel
-  size_t scratch_lane[2][2][2];  // [op][bwd][reduced] private bytes per lane
+  size_t scratch_lane[4][2][2];  // [kernel kind][bwd][reduced] private bytes per lane
   // twiddle tables (device, owned by the handle), one per table resolution
   cplx* tw[32];
   // pinned host staging for the per-call uploads and read-backs
@@ -112,6 +113,12 @@ constexpr size_t kMaxDispatchScratch = (size_t)96 << 20;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Kernel kinds: the three operator kinds, and the dense operator with the
+// direct (Cholesky) Newton solve.
+constexpr int kKindDirect = 3;
+constexpr int kKinds = 4;
+// Cap on the direct variant's per-team matrices (A^T A and M) of one call.
+constexpr size_t kDirectBudget = (size_t)32 << 30;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int check_params(const mfipm_params* p) {
@@ -124,6 +131,7 @@ int check_params(const mfipm_params* p) {
     return MFIPM_ERR_INVALID_ARG;
   if (std::isnan(p->rho)) return MFIPM_ERR_INVALID_ARG;
   if (p->reduced != 0 && p->reduced != 1) return MFIPM_ERR_INVALID_ARG;
+  if (p->direct != 0 && p->direct != 1) return MFIPM_ERR_INVALID_ARG;
   return MFIPM_OK;
 }
 
@@ -136,6 +144,12 @@ inline bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Team region layout for the largest instance of a call.  pt_chunks: chunk
 // capacity of the dense fused path's partial-product buffer.
+size_t direct_team_bytes(long long n) {
+  const size_t np = (size_t)((n + DC_NB - 1) / DC_NB * DC_NB);
+  return 2 * align_up(np * np * sizeof(double)) + align_up(np * DC_NB * sizeof(double)) +
+         align_up(np * sizeof(double));
+}
+
 TeamLayout team_layout(int op_kind, long long n, long long m, int pt_chunks) {
   TeamLayout L{};
   size_t off = 0;
@@ -152,7 +166,15 @@ TeamLayout team_layout(int op_kind, long long n, long long m, int pt_chunks) {
   take(L.DS, v2);
   take(L.Zs, v2);
   take(L.Ss, v2);
-  if (op_kind == MFIPM_OP_DENSE) {
+  L.DK = L.DM = L.DLi = L.DY = 0;
+  if (op_kind == kKindDirect) {
+    const size_t np = (size_t)((n + DC_NB - 1) / DC_NB * DC_NB);
+    take(L.DK, np * np * sizeof(double));
+    take(L.DM, np * np * sizeof(double));
+    take(L.DLi, np * DC_NB * sizeof(double));
+    take(L.DY, np * sizeof(double));
+  }
+  if (op_kind == MFIPM_OP_DENSE || op_kind == kKindDirect) {
     take(L.D, (size_t)n * sizeof(double));
     take(L.Yv, (size_t)m * sizeof(double));
     L.pt_chunks = n <= DN_FUSED_MAXN ? pt_chunks : 0;
@@ -225,9 +247,14 @@ int pt_chunks_for(const mfipm_handle* h, int bwd, int batch, long long m_max, in
   return (int)std::max(1LL, std::min(blocks, cap));
 }
 
-int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch, int red) {
+int max_teams_bound(const mfipm_handle* h, int op_kind, int bwd, int batch, int red, long long n_max) {
   const int gmax = std::max(1, h->occ[op_kind][bwd][red] * h->num_cu);
-  return std::max(1, std::min(batch, gmax));
+  int bound = std::max(1, std::min(batch, gmax));
+  if (op_kind == kKindDirect) {
+    const long long cap = (long long)(kDirectBudget / direct_team_bytes(n_max));
+    bound = (int)std::max(1LL, std::min<long long>(bound, cap));
+  }
+  return bound;
 }
 
 template <class OP, int BWD, bool RED>
@@ -236,7 +263,9 @@ const void* kernel_ptr() {
 }
 template <bool RED>
 const void* pick_kernel_r(int op_kind, int bwd) {
+  if (op_kind == kKindDirect) return kernel_ptr<OpDenseDirect, 0, true>();  // forward only
   if (op_kind == MFIPM_OP_DENSE) return bwd ? kernel_ptr<OpDense, 1, RED>() : kernel_ptr<OpDense, 0, RED>();
+  if (op_kind == MFIPM_OP_WHT) return bwd ? kernel_ptr<OpWht, 1, RED>() : kernel_ptr<OpWht, 0, RED>();
   return bwd ? kernel_ptr<OpPdct, 1, RED>() : kernel_ptr<OpPdct, 0, RED>();
 }
 const void* pick_kernel(int op_kind, int bwd, int red) {
@@ -246,7 +275,8 @@ const void* pick_kernel(int op_kind, int bwd, int red) {
 // (lo_bits / hi entries of the call, or the largest supported, n = 2^20).
 constexpr int kPdctMaxLog2N = 20;
 size_t dyn_lds(int op_kind, int lo_bits = -1, long long hi_count = 0) {
-  if (op_kind == MFIPM_OP_DENSE)
+  if (op_kind == MFIPM_OP_WHT) return (size_t)WH_TILE * sizeof(double);
+  if (op_kind == MFIPM_OP_DENSE || op_kind == kKindDirect)
     return (size_t)(MF_WAVES * DN_RBMAX + DN_RG * DN_CB) * sizeof(double) + DN_FUSED_MAXN * sizeof(double2);
   if (lo_bits < 0) {
     const int lm = kPdctMaxLog2N + 2;
@@ -293,6 +323,18 @@ const cplx* twiddle_tables(mfipm_handle* h, int lm, int lo_bits) {
 
 // Items of the widest pass of one instance (used to size a single team).
 long long widest_pass(int op_kind, long long n, long long m, int tile) {
+  if (op_kind == kKindDirect) {
+    // tiles of the lower block triangle (the A^T A product and the first updates)
+    const long long T = (n + DC_NB - 1) / DC_NB;
+    return std::max(widest_pass(MFIPM_OP_DENSE, n, m, tile), T * (T + 1) / 2);
+  }
+  if (op_kind == MFIPM_OP_WHT) {
+    // items of one column (pass A/C) or one row (pass B); at least one
+    // workgroup per 4096 indices
+    const int ln = ilog2_host(n);
+    const long long N1 = 1LL << (ln / 2), N2 = n / N1;
+    return std::max(std::max(N1, N2) / 4, std::max(1LL, n >> 12));
+  }
   if (op_kind == MFIPM_OP_DENSE) {
     if (n <= DN_FUSED_MAXN) {
       // about 256 KiB of A per workgroup, at least 32 and at most one block each
@@ -326,13 +368,14 @@ struct Problem {
 int validate(const mfipm_handle* h, const Problem& P) {
   if (!h) return MFIPM_ERR_INVALID_ARG;
   if (P.batch < 1 || !P.n_off || !P.m_off) return MFIPM_ERR_INVALID_ARG;
-  if (P.op_kind != MFIPM_OP_DENSE && P.op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind != MFIPM_OP_DENSE && P.op_kind != MFIPM_OP_PDCT && P.op_kind != MFIPM_OP_WHT)
+    return MFIPM_ERR_INVALID_ARG;
   if (P.op_kind == MFIPM_OP_DENSE && !P.shared_op && !P.a_off) return MFIPM_ERR_INVALID_ARG;
   for (int i = 0; i < P.batch; ++i) {
     const long long n = P.n_off[i + 1] - P.n_off[i];
     const long long m = P.m_off[i + 1] - P.m_off[i];
     if (n < 1 || m < 1 || P.n_off[i] < 0 || P.m_off[i] < 0) return MFIPM_ERR_INVALID_ARG;
-    if (P.op_kind == MFIPM_OP_PDCT) {
+    if (P.op_kind != MFIPM_OP_DENSE) {
       if (!is_pow2(n) || n < 64 || n > (1LL << kPdctMaxLog2N) || m > n) return MFIPM_ERR_INVALID_ARG;
     } else if (!P.shared_op && P.a_off[i + 1] - P.a_off[i] != n * m) {
       return MFIPM_ERR_INVALID_ARG;
@@ -407,18 +450,25 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   if (rc) return rc;
   if (!ws) return MFIPM_ERR_INVALID_ARG;
   if (P.op_kind == MFIPM_OP_DENSE && !A) return MFIPM_ERR_INVALID_ARG;
-  if (P.op_kind == MFIPM_OP_PDCT && !rows) return MFIPM_ERR_INVALID_ARG;
+  if (P.op_kind != MFIPM_OP_DENSE && !rows) return MFIPM_ERR_INVALID_ARG;
   if (!bwd && (!b || !x)) return MFIPM_ERR_INVALID_ARG;
   if (bwd && !state) return MFIPM_ERR_NO_STATE;
   if (bwd && (!grad_x || !grad_b || !grad_tau)) return MFIPM_ERR_INVALID_ARG;
 
+  // kernel kind: the forward solve with direct Newton solves is its own kernel
+  int kind = P.op_kind;
+  int red = h->prm.reduced;
+  if (!bwd && h->prm.direct) {
+    if (P.op_kind != MFIPM_OP_DENSE || P.n_max > DC_MAX_N) return MFIPM_ERR_INVALID_ARG;
+    kind = kKindDirect;
+    red = 1;  // the direct solve works on the n x n system
+  }
   // launch shape
-  const int red = h->prm.reduced;
-  if (h->occ[P.op_kind][bwd][red] < 1) return MFIPM_ERR_HIP;
-  const int gmax = std::max(1, h->occ[P.op_kind][bwd][red] * h->num_cu);
+  if (h->occ[kind][bwd][red] < 1) return MFIPM_ERR_HIP;
+  const int gmax = std::max(1, h->occ[kind][bwd][red] * h->num_cu);
   int team_size, num_teams;
   if (P.batch == 1) {
-    long long want = h->req_wg > 0 ? h->req_wg : widest_pass(P.op_kind, P.n_max, P.m_max, h->req_tile);
+    long long want = h->req_wg > 0 ? h->req_wg : widest_pass(kind, P.n_max, P.m_max, h->req_tile);
     team_size = (int)std::max(1LL, std::min<long long>(want, gmax));
     num_teams = 1;
   } else {
@@ -431,13 +481,21 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     num_teams = std::max(1, std::min(P.batch, total / team_size));
   }
   if (team_size > MF_MAX_TEAM) team_size = MF_MAX_TEAM;
-  const int teams_bound = max_teams_bound(h, P.op_kind, bwd, P.batch, red);
+  const int teams_bound = max_teams_bound(h, kind, bwd, P.batch, red, P.n_max);
   if (num_teams > teams_bound) num_teams = teams_bound;
-  if (h->scratch_lane[P.op_kind][bwd][red] * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch)
-    return MFIPM_ERR_HIP;
+  // private memory of the whole grid within the dispatch limit: fewer teams,
+  // then smaller ones
+  const size_t lane_scr = h->scratch_lane[kind][bwd][red];
+  if (lane_scr > 0) {
+    const long long max_wg = (long long)(kMaxDispatchScratch / (lane_scr * MF_THREADS));
+    if (max_wg < 1) return MFIPM_ERR_HIP;
+    if ((long long)num_teams * team_size > max_wg) num_teams = (int)std::max(1LL, max_wg / team_size);
+    if ((long long)num_teams * team_size > max_wg) team_size = (int)max_wg;
+  }
+  if (lane_scr * MF_THREADS * (size_t)(num_teams * team_size) > kMaxDispatchScratch) return MFIPM_ERR_HIP;
 
-  const TeamLayout tl = team_layout(P.op_kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max, red));
-  GlobalLayout gl = global_layout(P.op_kind, P.n_max, P.batch, teams_bound, tl);
+  const TeamLayout tl = team_layout(kind, P.n_max, P.m_max, pt_chunks_for(h, bwd, P.batch, P.m_max, red));
+  GlobalLayout gl = global_layout(kind, P.n_max, P.batch, teams_bound, tl);
   if (ws_bytes < gl.total) return noalloc ? MFIPM_ERR_TOO_LARGE : MFIPM_ERR_WORKSPACE_TOO_SMALL;
   int tw_log2n_max = ilog2_host(P.n_max);
   if (noalloc && P.op_kind == MFIPM_OP_PDCT) {
@@ -545,8 +603,8 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   void* args[] = {&a};
   const int grid = num_teams * team_size;
   if (hipEventRecord(h->ev0, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
-  if (hipLaunchCooperativeKernel(pick_kernel(P.op_kind, bwd, red), dim3(grid), dim3(MF_THREADS), args,
-                                 (unsigned)dyn_lds(P.op_kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
+  if (hipLaunchCooperativeKernel(pick_kernel(kind, bwd, red), dim3(grid), dim3(MF_THREADS), args,
+                                 (unsigned)dyn_lds(kind, gl.lo_bits, gl.hi_count), s) != hipSuccess)
     return fail(MFIPM_ERR_HIP);
   if (hipEventRecord(h->ev1, s) != hipSuccess) return fail(MFIPM_ERR_HIP);
   const DevInfo* dinf = reinterpret_cast<const DevInfo*>(stage);
@@ -599,7 +657,7 @@ LsLayout ls_layout(long long n, long long m, int B) {
 }
 
 bool use_lockstep(const mfipm_handle* h, int op_kind, int shared_op, int batch) {
-  return op_kind == MFIPM_OP_DENSE && shared_op && batch >= kLockstepMinBatch &&
+  return op_kind == MFIPM_OP_DENSE && shared_op && batch >= kLockstepMinBatch && !h->prm.direct &&
          batch <= LS_MAX_GROUPS * LS_TN && h->req_team <= 0 && !h->prm.reduced;
 }
 
@@ -712,6 +770,7 @@ int mfipm_params_default(mfipm_params* p) {
   p->mxiterpcg_adj = 1000;
   p->step_min = 1e-14;
   p->reduced = 0;
+  p->direct = 0;
   return MFIPM_OK;
 }
 
@@ -738,7 +797,7 @@ int mfipm_create(mfipm_handle** hp, const mfipm_params* p, void* stream) {
     return MFIPM_ERR_HIP;
   }
   h->wall_khz = wclk > 0 ? wclk : 100000;
-  for (int op = 0; op < 2; ++op)
+  for (int op = 0; op < kKinds; ++op)
     for (int bwd = 0; bwd < 2; ++bwd)
       for (int red = 0; red < 2; ++red) {
       int occ = 0;
@@ -810,14 +869,21 @@ double mfipm_last_kernel_ms(const mfipm_handle* h) { return h ? h->last_ms : -1.
 int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, int64_t max_m, int32_t batch,
                          size_t* bytes) {
   if (!h || !bytes || batch < 1 || max_n < 1 || max_m < 1) return MFIPM_ERR_INVALID_ARG;
-  if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT) return MFIPM_ERR_INVALID_ARG;
+  if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT && op_kind != MFIPM_OP_WHT) return MFIPM_ERR_INVALID_ARG;
   size_t best = 0;
   for (int bwd = 0; bwd < 2; ++bwd)
     for (int red = 0; red < 2; ++red) {
       const TeamLayout tl = team_layout(op_kind, max_n, max_m, pt_chunks_for(h, bwd, batch, max_m, red));
-      const GlobalLayout gl = global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch, red), tl);
+      const GlobalLayout gl =
+          global_layout(op_kind, max_n, batch, max_teams_bound(h, op_kind, bwd, batch, red, max_n), tl);
       best = std::max(best, gl.total);
     }
+  if (op_kind == MFIPM_OP_DENSE && h->prm.direct && max_n <= DC_MAX_N) {
+    const TeamLayout tl = team_layout(kKindDirect, max_n, max_m, pt_chunks_for(h, 0, batch, max_m, 1));
+    const GlobalLayout gl =
+        global_layout(kKindDirect, max_n, batch, max_teams_bound(h, kKindDirect, 0, batch, 1, max_n), tl);
+    best = std::max(best, gl.total);
+  }
   if (op_kind == MFIPM_OP_DENSE && batch >= kLockstepMinBatch) best = std::max(best, ls_layout(max_n, max_m, batch).total);
   *bytes = best;
   return MFIPM_OK;

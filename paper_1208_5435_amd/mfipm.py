@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libmfipm.so")
 
 OP_DENSE = 0
 OP_PDCT = 1
+OP_WHT = 2
+TRANSFORMS = {"dct": OP_PDCT, "wht": OP_WHT}
 
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "PCG_BREAKDOWN", 3: "NONFINITE", 4: "STEP_UNDERFLOW",
           5: "ABORTED", 6: "INPUT_CHECK", 7: "PCG_MAXITER"}
@@ -40,7 +42,8 @@ class Params(ctypes.Structure):
                 ("eta", ctypes.c_double), ("rho", ctypes.c_double),
                 ("z0", ctypes.c_double), ("s0", ctypes.c_double),
                 ("tolpcg_adj", ctypes.c_double), ("mxiterpcg_adj", ctypes.c_int32),
-                ("step_min", ctypes.c_double), ("reduced", ctypes.c_int32)]
+                ("step_min", ctypes.c_double), ("reduced", ctypes.c_int32),
+                ("direct", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -229,9 +232,10 @@ class Solver:
         return self._ws, nbytes.value
 
     # -- single instance ------------------------------------------------------
-    def solve(self, b, tau, A=None, rows=None, n=None, want_state=True) -> Result:
+    def solve(self, b, tau, A=None, rows=None, n=None, want_state=True, transform="dct") -> Result:
         """Solves min tau||x||_1 + 1/2||Ax-b||^2 with a dense A (m x n, float64,
-        contiguous) or a partial DCT (rows: int32 sorted distinct, length n)."""
+        contiguous) or rows of a fast transform of length n (rows: int32 sorted
+        distinct; transform "dct" or "wht")."""
         torch = self.torch
         b = _dev(b, self.device, torch.float64)
         if A is not None:
@@ -242,8 +246,8 @@ class Solver:
         else:
             rows = _dev(rows, self.device, torch.int32)
             m = rows.shape[0]
-            op = Operator(OP_PDCT, m, int(n), None, 0, rows.data_ptr())
-            kind = OP_PDCT
+            kind = _transform(transform)
+            op = Operator(kind, m, int(n), None, 0, rows.data_ptr())
         if b.shape[0] != m:
             raise ValueError("b has the wrong length")
         x = torch.empty(int(op.n), dtype=torch.float64, device=self.device)
@@ -256,7 +260,7 @@ class Solver:
         _check("mfipm_solve", rc)
         return Result(x=x, state=state, infos=[info.as_dict()], kernel_ms=self.last_kernel_ms())
 
-    def solve_noalloc(self, b, tau, x, state=None, A=None, rows=None, n=None) -> dict:
+    def solve_noalloc(self, b, tau, x, state=None, A=None, rows=None, n=None, transform="dct") -> dict:
         """mfipm_solve_noalloc: like `solve`, but the library uses its static
         per-device scratch instead of a workspace and allocates nothing; the
         caller passes device tensors for b, x (n) and optionally state (4n).
@@ -265,7 +269,7 @@ class Solver:
             m, nn = A.shape
             op = Operator(OP_DENSE, m, nn, A.data_ptr(), nn, None)
         else:
-            op = Operator(OP_PDCT, rows.shape[0], int(n), None, 0, rows.data_ptr())
+            op = Operator(_transform(transform), rows.shape[0], int(n), None, 0, rows.data_ptr())
         if b.shape[0] != op.m or x.shape[0] != op.n or (state is not None and state.shape[0] != 4 * op.n):
             raise ValueError("b, x or state has the wrong length")
         for t in (b, x, state, A, rows):
@@ -281,13 +285,13 @@ class Solver:
 
     # -- batches ----------------------------------------------------------------
     def solve_batched(self, b_packed, tau, n_off, m_off, A_packed=None, a_off=None, rows=None,
-                      shared_op=False, want_state=True) -> Result:
+                      shared_op=False, want_state=True, transform="dct") -> Result:
         torch = self.torch
         batch = len(n_off) - 1
         n_off = np.ascontiguousarray(n_off, dtype=np.int64)
         m_off = np.ascontiguousarray(m_off, dtype=np.int64)
         tau = np.ascontiguousarray(tau, dtype=np.float64)
-        kind = OP_DENSE if A_packed is not None else OP_PDCT
+        kind = OP_DENSE if A_packed is not None else _transform(transform)
         if kind == OP_DENSE and not shared_op:
             a_off = np.ascontiguousarray(a_off, dtype=np.int64)
         else:
@@ -312,13 +316,14 @@ class Solver:
         _check("mfipm_solve_batched", rc)
         return Result(x=x, state=state, infos=[i.as_dict() for i in infos], kernel_ms=self.last_kernel_ms())
 
-    def backward(self, state, grad_x, n_off, m_off, A_packed=None, a_off=None, rows=None, shared_op=False):
+    def backward(self, state, grad_x, n_off, m_off, A_packed=None, a_off=None, rows=None, shared_op=False,
+                 transform="dct"):
         """Adjoint at `state`: returns (grad_b packed, grad_tau per instance, infos)."""
         torch = self.torch
         batch = len(n_off) - 1
         n_off = np.ascontiguousarray(n_off, dtype=np.int64)
         m_off = np.ascontiguousarray(m_off, dtype=np.int64)
-        kind = OP_DENSE if A_packed is not None else OP_PDCT
+        kind = OP_DENSE if A_packed is not None else _transform(transform)
         if kind == OP_DENSE and not shared_op:
             a_off = np.ascontiguousarray(a_off, dtype=np.int64)
         else:
@@ -340,6 +345,13 @@ class Solver:
             1 if shared_op else 0, _ptr(state), _ptr(grad_x), _ptr(grad_b), _ptr(grad_tau), _ptr(ws), nb, infos)
         _check("mfipm_backward", rc)
         return grad_b, grad_tau, [i.as_dict() for i in infos]
+
+
+def _transform(name):
+    try:
+        return TRANSFORMS[name]
+    except KeyError:
+        raise ValueError(f"unknown transform {name!r}; expected one of {sorted(TRANSFORMS)}") from None
 
 
 def _dev(t, device, dtype):

@@ -245,3 +245,22 @@ def pin_reduced_vs_direct(A, b, tau):
     r1 = R.solve(op, b, tau, p_it)
     r2 = R.solve(op, b, tau, p_it, linsolve="direct")
     return abs(r1.ipm_iters - r2.ipm_iters), float(np.linalg.norm(r1.x - r2.x) / np.linalg.norm(r2.x))
+
+
+def pin_wht_definition(n, m, seed):
+    """Partial Walsh-Hadamard operator against the matrix entries written
+    out from their closed form, H[k, j] = (-1)^{popcount(k & j)} (Sylvester
+    order), the adjoint identity and A A^T = I.  Returns the largest error."""
+    rng = rng_for(seed)
+    rows = np.sort(rng.choice(n, m, replace=False))
+    op = R.PartialWHTOperator(n, rows)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    j = np.arange(n)
+    ref = np.array([np.sum(x * (-1.0) ** np.array([bin(int(k) & int(jj)).count("1") for jj in j]))
+                    for k in rows]) / math.sqrt(n)
+    e1 = np.linalg.norm(op.matvec(x) - ref) / np.linalg.norm(ref)
+    e2 = abs(op.matvec(x) @ y - x @ op.rmatvec(y)) / (np.linalg.norm(x) * np.linalg.norm(y))
+    e3 = np.linalg.norm(op.matvec(op.rmatvec(y)) - y) / np.linalg.norm(y)
+    e4 = np.linalg.norm(op.dense() @ x - op.matvec(x)) / np.linalg.norm(ref)
+    return max(e1, e2, e3, e4)

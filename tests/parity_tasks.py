@@ -73,3 +73,14 @@ def shared_dense_signal(j, x, state, info, batch):
     ref = U.check_against_oracle(op, inst.b[0], inst.tau[0], x, info, state, label=f"shared_dense[{j}]",
                                  strict=True)
     return j, ref.ipm_iters, info["ipm_iters"], U.rel(x, ref.x)
+
+
+def phase_instance(n, rows, b, tau, x_true, x_gpu, info):
+    """One phase-transition instance: the oracle's solve at the sweep's
+    parameters.  Returns (oracle status, oracle IPM iterations, oracle r.e.,
+    GPU r.e., rel(x_gpu, x_oracle))."""
+    op = R.PartialDCTOperator(n, rows)
+    ref = R.solve(op, b, tau, R.Params(**W.PHASE_PARAMS))
+    re_o = float(np.linalg.norm(ref.x - x_true) / np.linalg.norm(x_true))
+    re_g = float(np.linalg.norm(x_gpu - x_true) / np.linalg.norm(x_true))
+    return ref.status, ref.ipm_iters, re_o, re_g, U.rel(x_gpu, ref.x)

@@ -259,3 +259,25 @@ def test_reduced_adjoint_matches_dense():
     g2 = R.backward(op, res.z, res.s, res.x - xt, method="dense")
     assert np.linalg.norm(g1.grad_b - g2.grad_b) <= 1e-8 * np.linalg.norm(g2.grad_b)
     assert abs(g1.grad_tau - g2.grad_tau) <= 1e-8 * abs(g2.grad_tau)
+
+
+@pytest.mark.parametrize("n,m", [(64, 16), (256, 100)])
+def test_wht_definition(n, m):
+    assert PIN.pin_wht_definition(n, m, seed=n + 3) <= 1e-12
+
+
+def test_wht_full_soft_threshold():
+    """All rows of the orthonormal Walsh-Hadamard matrix: x* = soft(W b, tau)."""
+    rng = PIN.rng_for(61)
+    n = 128
+    op = R.PartialWHTOperator(n, np.arange(n))
+    b = rng.standard_normal(n)
+    assert PIN.pin_orthonormal_soft_threshold(op, b, 0.5) <= 1e-7
+
+
+@pytest.mark.parametrize("kind", ["wht"])
+def test_wht_newton_blocks_and_theorem(kind):
+    rng = PIN.rng_for(62)
+    n = 32
+    op = R.PartialWHTOperator(n, np.sort(rng.choice(n, 8, replace=False)))
+    assert PIN.pin_newton_blocks(op, seed=4) <= 1e-7

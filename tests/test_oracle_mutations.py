@@ -213,3 +213,20 @@ def test_reduced_rhs_slip_caught(monkeypatch):
         return tu * tv / (tu + tv), (tv * rhs[:n] + tu * rhs[n:]) / (tu + tv)
     monkeypatch.setattr(R, "reduced_system", bad)
     assert PIN.pin_reduced_direction(_small_ops()[1], seed=5) > 1e-3
+
+
+def test_wht_ordering_slip_caught(monkeypatch):
+    """A transform in the wrong order (pairs combined as (a - b, a + b))."""
+    def bad_fwht(x):
+        y = np.array(x, dtype=np.float64, copy=True)
+        n = y.shape[0]
+        h = 1
+        while h < n:
+            y = y.reshape(-1, 2, h)
+            a = y[:, 0, :].copy()
+            b = y[:, 1, :]
+            y = np.stack([a - b, a + b], axis=1).reshape(n)
+            h *= 2
+        return y
+    monkeypatch.setattr(R, "fwht", bad_fwht)
+    assert PIN.pin_wht_definition(64, 16, seed=67) > 1e-3

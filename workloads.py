@@ -15,7 +15,10 @@ Operators:
   * partial DCT: A = R_m C, where C is the orthonormal DCT-II of length n and
     R_m keeps m distinct rows drawn uniformly without replacement, sorted
     ascending (paper, Section 2 orthonormal rows, eq. (eq:orthonormality), and
-    Section 5.8 phase-transition setup "normalized DCT").
+    Section 5.8 phase-transition setup "normalized DCT");
+  * partial Walsh-Hadamard: A = R_m W, W = H_n / sqrt(n) with H_n the
+    Sylvester-ordered Hadamard matrix, rows drawn as for the DCT (another fast
+    orthonormal transform, paper Sections 1-2).
 
 Draw order inside one instance is fixed: operator (A or rows) -> support ->
 amplitudes / signs -> noise.  Every generator is numpy's PCG64 with the stated
@@ -34,6 +37,8 @@ __all__ = [
     "config_dense_256x1024", "config_pdct", "config_pdct_hdr",
     "batched_dense_sizes", "batched_dense_instance", "config_dct_batch",
     "dct_apply", "dct_apply_t", "SharedDenseInstance", "config_shared_dense",
+    "wht_apply", "wht_apply_t", "config_wht", "config_wht_hdr", "direct_scaling_instance",
+    "DIRECT_SCALING_NS",
 ]
 
 
@@ -47,6 +52,33 @@ def dct_apply_t(rows: np.ndarray, n: int, y: np.ndarray) -> np.ndarray:
     full = np.zeros(n, np.float64)
     full[rows] = y
     return scipy.fft.idct(full, type=2, norm="ortho")
+
+
+def _hadamard_unnormalised(x: np.ndarray) -> np.ndarray:
+    """H_n x for the Sylvester-ordered Hadamard matrix (input synthesis only)."""
+    v = np.array(x, np.float64, copy=True)
+    n = v.shape[0]
+    h = 1
+    while h < n:
+        v = v.reshape(-1, 2, h)
+        v = np.stack([v[:, 0] + v[:, 1], v[:, 0] - v[:, 1]], axis=1).reshape(n)
+        h *= 2
+    return v
+
+
+def wht_apply(rows: np.ndarray, n: int, x: np.ndarray) -> np.ndarray:
+    """Rows `rows` of H_n x / sqrt(n) (input synthesis only)."""
+    return _hadamard_unnormalised(x)[rows] / np.sqrt(n)
+
+
+def wht_apply_t(rows: np.ndarray, n: int, y: np.ndarray) -> np.ndarray:
+    """Transpose of wht_apply: zero-fill to length n, then H_n / sqrt(n)."""
+    full = np.zeros(n, np.float64)
+    full[rows] = y
+    return _hadamard_unnormalised(full) / np.sqrt(n)
+
+
+_APPLY = {"dct": (dct_apply, dct_apply_t), "wht": (wht_apply, wht_apply_t)}
 
 
 def _sparse_signal(rng: np.random.Generator, n: int, k: int, amp: str) -> np.ndarray:
@@ -93,6 +125,7 @@ class DCTInstance:
     seed: int
     label: str = ""
     extra: dict = field(default_factory=dict)
+    transform: str = "dct"  # "dct" or "wht": which transform's rows A keeps
 
     @property
     def m(self) -> int:
@@ -111,14 +144,17 @@ def dense_instance(m: int, n: int, k: int, seed: int, amp: str = "normal",
 
 
 def dct_instance(n: int, m: int, k: int, seed: int, amp: str = "normal",
-                 sigma: float = 1e-2, c_tau: float = 1e-2, label: str = "") -> DCTInstance:
+                 sigma: float = 1e-2, c_tau: float = 1e-2, label: str = "",
+                 transform: str = "dct") -> DCTInstance:
+    """Rows of a fast transform ("dct" or "wht"), a k-sparse signal, noise."""
+    fwd, adj = _APPLY[transform]
     rng = np.random.default_rng(np.random.PCG64(seed))
     rows = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
     x = _sparse_signal(rng, n, k, amp)
     e = sigma * rng.standard_normal(m)
-    b = dct_apply(rows, n, x) + e
-    tau = float(c_tau * np.max(np.abs(dct_apply_t(rows, n, b))))
-    return DCTInstance(n=n, rows=rows, b=b, tau=tau, x_true=x, seed=seed, label=label)
+    b = fwd(rows, n, x) + e
+    tau = float(c_tau * np.max(np.abs(adj(rows, n, b))))
+    return DCTInstance(n=n, rows=rows, b=b, tau=tau, x_true=x, seed=seed, label=label, transform=transform)
 
 
 # --- the five named workloads -------------------------------------------------
@@ -141,6 +177,35 @@ def config_pdct_hdr(n: int = 1 << 20) -> DCTInstance:
                         label=f"pdct_hdr_n{n}")
 
 
+def config_wht(n: int = 1 << 16) -> DCTInstance:
+    """Partial Walsh-Hadamard n=2^16 with the partial-DCT n=2^16 recipe."""
+    return dct_instance(n, n // 4, n // 100, seed=120809, amp="normal", sigma=1e-2, c_tau=1e-2,
+                        label=f"wht_n{n}", transform="wht")
+
+
+def config_wht_hdr(n: int = 1 << 20) -> DCTInstance:
+    """Partial Walsh-Hadamard n=2^20 with the high-dynamic-range partial-DCT recipe."""
+    return dct_instance(n, n // 4, n // 200, seed=120810, amp="hdr", sigma=1e-3, c_tau=1e-3,
+                        label=f"wht_hdr_n{n}", transform="wht")
+
+
+# Section 5.7 (direct solver against PCG): n = 2^5 .. 2^12, m = n/4.
+DIRECT_SCALING_NS = tuple(1 << e for e in range(5, 13))
+
+
+def direct_scaling_instance(n: int, seed: int = 120811) -> DenseInstance:
+    """The Section 5.7 comparison problem: Gaussian A (N(0, 1/m), m = n/4),
+    k = ceil(m/20) nonzeros at random positions with N(0,1) values,
+    noiseless b = A x, tau = 1e-3 (absolute)."""
+    m = n // 4
+    k = -(-m // 20)
+    rng = np.random.default_rng(np.random.PCG64(seed * 100 + int(np.log2(n))))
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    x = _sparse_signal(rng, n, k, "normal")
+    b = A @ x
+    return DenseInstance(A=np.ascontiguousarray(A), b=b, tau=1e-3, x_true=x, seed=seed, label=f"direct_n{n}")
+
+
 def batched_dense_sizes(batch: int = 256, seed: int = 120804) -> np.ndarray:
     """Signal lengths n_i = 64 * U{16..128} of the batched dense workload."""
     rng = np.random.default_rng(np.random.PCG64(seed))
@@ -154,8 +219,10 @@ def batched_dense_instance(i: int, n: int, seed: int = 120804) -> DenseInstance:
 
 
 def config_dct_batch(n: int = 1 << 18, batch: int = 32, seed: int = 120805,
-                     sigma: float = 1e-2, c_tau: float = 5e-3) -> DCTInstance:
-    """`batch` signals sharing one partial DCT (m=n/4), k=floor(n/100) N(0,1)."""
+                     sigma: float = 1e-2, c_tau: float = 5e-3, transform: str = "dct") -> DCTInstance:
+    """`batch` signals sharing one partial DCT (or Walsh-Hadamard: transform
+    "wht") with m=n/4, k=floor(n/100) N(0,1)."""
+    dct_apply, dct_apply_t = _APPLY[transform]
     rng = np.random.default_rng(np.random.PCG64(seed))
     m, k = n // 4, n // 100
     rows = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
@@ -171,7 +238,8 @@ def config_dct_batch(n: int = 1 << 18, batch: int = 32, seed: int = 120805,
     direction = drng.standard_normal((batch, m))
     direction /= np.linalg.norm(direction, axis=1, keepdims=True)
     return DCTInstance(n=n, rows=rows, b=Bm, tau=taus, x_true=X, seed=seed,
-                       label=f"pdct_batch{batch}_n{n}", extra={"fd_direction": direction})
+                       label=f"p{transform}_batch{batch}_n{n}", extra={"fd_direction": direction},
+                       transform=transform)
 
 
 def config_shared_dense(m: int = 2048, n: int = 8192, batch: int = 256, seed: int = 120806,
@@ -214,3 +282,31 @@ class SharedDenseInstance:
     @property
     def n(self) -> int:
         return self.A.shape[1]
+
+
+# --- phase-transition sweep --------------------------------------------------
+
+PHASE_PARAMS = dict(tol=1e-12, tolpcg=1e-6)  # noiseless ranges of the tuning section
+PHASE_C_TAU = 1e-6
+
+
+def phase_transition_grid(n: int = 1024, deltas=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9),
+                          rhos=None, trials: int = 10, seed: int = 120807):
+    """Noiseless partial-DCT instances over a grid of undersampling
+    delta = m/n and sparsity rho = k/m (the average phase-transition
+    experiment: m random rows of the orthonormal DCT, k spikes of +-1 at
+    random positions, b = A x exactly).  Instance (delta index i, rho index j,
+    trial t) draws from PCG64(seed * 10^6 + 10^4 i + 100 j + t).  Returns a
+    list of (delta, rho, trial, DCTInstance); tau = 1e-6 ||A^T b||_inf."""
+    if rhos is None:
+        rhos = tuple(round(0.05 * i, 2) for i in range(1, 20))
+    out = []
+    for i, d in enumerate(deltas):
+        m = max(1, int(round(d * n)))
+        for j, r in enumerate(rhos):
+            k = max(1, int(round(r * m)))
+            for t in range(trials):
+                inst = dct_instance(n, m, k, seed=seed * 10 ** 6 + 10 ** 4 * i + 100 * j + t, amp="pm1",
+                                    sigma=0.0, c_tau=PHASE_C_TAU, label=f"phase_d{d}_r{r}_t{t}")
+                out.append((d, r, t, inst))
+    return out
