@@ -76,7 +76,19 @@ struct Twiddle {
 // release) and arrives on the top counter; the last top arrival publishes the
 // generation in a release word on which everyone waits, then acquires
 // (invalidating its L2 and L1 view).  One write-back per XCD instead of one
-// per workgroup is what makes the release side cheap.  Counters only grow
+// per workgroup is what makes the release side cheap.
+//
+// This relies on the hardware, not on the C++/HIP memory model (in which a
+// relaxed counter increment does not carry another workgroup's stores): the
+// LLVM AMDGPU backend's memory-model description for the GFX942 family
+// (AMDGPUUsage, "Memory Model GFX942", which gfx950 follows) implements an
+// agent-scope release as "s_waitcnt vmcnt(0)" followed by "buffer_wbl2 sc1",
+// and buffer_wbl2 writes back every dirty line of the L2 of the XCD that
+// executes it, not only the issuing wave's; an agent-scope acquire is
+// "buffer_inv sc1", which invalidates that XCD's L2 and the CU's L1.  Each
+// member of a group has its stores complete in the shared L2 (its own
+// s_waitcnt) before its arrival is counted, so the last arrival's write-back
+// covers them.  Counters only grow
 // (targets are generation * count), so nothing is reset between barriers.
 // Every wait is bounded in wall-clock time: past the bound a global abort flag
 // is raised, later barriers return at once and the solver loops stop, so the
