@@ -16,7 +16,8 @@ grad (32 signals sharing a partial DCT, n = 2^18, forward + adjoint),
 shared_dense (256 signals sharing one 2048 x 8192 dense A, FP64 MFMA),
 phase (a phase-transition sweep of small partial-DCT instances),
 pdct (partial DCT n = 2^16), dense (256 x 1024), wht / wht_hdr (partial
-Walsh-Hadamard n = 2^16 / 2^20, with the recipes of pdct / pdct_hdr),
+Walsh-Hadamard n = 2^16 / 2^20, with the recipes of pdct / pdct_hdr), dst
+(partial DST-II n = 2^16, the pdct recipe),
 direct (exact Newton directions by Cholesky, n = 4096, with the n = 2^5 ..
 2^12 sweep of both variants).
 
@@ -53,7 +54,7 @@ METRIC = "l1-LS solves/sec + PCG matvec HBM GB/s (% peak), batched & grad vs pla
 
 
 def alg_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
-    op = 16.0 * (n + m) if kind in ("pdct", "wht") else 8.0 * m * n
+    op = 16.0 * (n + m) if kind in ("pdct", "wht", "dst") else 8.0 * m * n
     vec = 56.0 * n if reduced else 112.0 * n  # reduced: x, r, p, Theta_bar^{-1} are n-vectors
     pcg = info["pcg_iters"] * (vec + op)
     ipm = (info["ipm_iters"] + info["correctors"] + 1) * (160.0 * n + op)
@@ -61,7 +62,7 @@ def alg_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> f
 
 
 def adjoint_bytes(kind: str, n: int, m: int, info: dict, reduced: bool = False) -> float:
-    op = 16.0 * (n + m) if kind in ("pdct", "wht") else 8.0 * m * n
+    op = 16.0 * (n + m) if kind in ("pdct", "wht", "dst") else 8.0 * m * n
     vec = 56.0 * n if reduced else 112.0 * n
     return info["pcg_iters"] * (vec + op) + 2 * (160.0 * n + op)
 
@@ -111,12 +112,17 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str, calib_mb: int):
         if not copies or not solves:
             raise SystemExit(f"{path}: no calibration copy or no solve kernel in the counter file")
         scale = (calib_mb << 20) / (max(copies) * 1024.0)
-        vals = [float(r["Counter_Value"]) for r in solves]
+        # one step may launch several solve kernels (forward and adjoint): the
+        # per-step figure is the sum over kernels of each one's mean per launch
+        by_kernel = {}
+        for r in solves:
+            by_kernel.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        kib = sum(float(np.mean(v)) for v in by_kernel.values())
         rec[f"{what}_scale"] = scale
-        rec[f"{what}_bytes_per_launch"] = float(np.mean(vals)) * 1024.0 * scale
-        rec[f"{what}_kib_raw_per_launch"] = float(np.mean(vals))
-        rec["kernel"] = solves[0]["Kernel_Name"]
-        rec["launches"] = len(solves)
+        rec[f"{what}_bytes_per_launch"] = kib * 1024.0 * scale
+        rec[f"{what}_kib_raw_per_launch"] = kib
+        rec["kernel"] = " + ".join(sorted(by_kernel))
+        rec["launches"] = {k: len(v) for k, v in sorted(by_kernel.items())}
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -176,6 +182,8 @@ def cpu_baseline_single(kind, inst, budget_s):
         op = R.DenseOperator(inst.A)
     elif kind == "wht":
         op = R.PartialWHTOperator(inst.n, inst.rows)
+    elif kind == "dst":
+        op = R.PartialDSTOperator(inst.n, inst.rows)
     else:
         op = R.PartialDCTOperator(inst.n, inst.rows)
     times = []
@@ -292,6 +300,9 @@ def make_single(name: str):
     if name == "pdct_hdr":
         inst = W.config_pdct_hdr()
         return "pdct", inst, f"pdct_hdr_n{inst.n}_m{inst.m}_k{inst.n // 200}"
+    if name == "dst":
+        inst = W.config_dst()
+        return "dst", inst, f"dst_n{inst.n}_m{inst.m}_k{inst.n // 100}"
     if name == "wht":
         inst = W.config_wht()
         return "wht", inst, f"wht_n{inst.n}_m{inst.m}_k{inst.n // 100}"
@@ -331,7 +342,8 @@ def bench_single(args, torch, Solver):
            "ipm_iters": info["ipm_iters"], "pcg_iters": info["pcg_iters"], "correctors": info["correctors"],
            "nmat": info["nmat"], "rel_gap": info["rel_gap"], "kernel_ms_mean": round(kms_mean, 4),
            "kernel_ms_min": round(float(np.min(kms)), 4)}
-    kern = {"pdct": "k_mfipm<OpPdct,0>", "wht": "k_mfipm<OpWht,0>", "dense": "k_mfipm<OpDense,0>"}[kind]
+    kern = {"pdct": "k_mfipm<OpPdct,0>", "dst": "k_mfipm<OpPdct,0>", "wht": "k_mfipm<OpWht,0>",
+            "dense": "k_mfipm<OpDense,0>"}[kind]
     out = _line(round(args.steps / wall, 3), "solves/s", args, 1e3 * wall / args.steps, cfg,
                 _hbm_roofline(alg_bytes(kind, n, m, info, args.reduced), kms_mean, kern, wl))
     if not args.no_cpu_baseline:
@@ -649,7 +661,7 @@ def tune_workload(args, torch, Solver):
     solver = Solver(device=dev, params=_params(args))
     out = args.tune_out or autotune.SHIPPED
     jobs = []
-    if args.workload in ("pdct", "pdct_hdr", "wht", "wht_hdr", "dense"):
+    if args.workload in ("pdct", "pdct_hdr", "wht", "wht_hdr", "dst", "dense"):
         kind, inst, _ = make_single(args.workload)
         b = torch.from_numpy(inst.b).to(dev)
         if kind == "dense":
@@ -659,7 +671,7 @@ def tune_workload(args, torch, Solver):
         else:
             rows = torch.from_numpy(inst.rows).to(dev)
             call = lambda: solver.solve(b, inst.tau, rows=rows, n=inst.n, transform=inst.transform)  # noqa: E731
-            op = 2 if kind == "wht" else 1
+            op = {"wht": 2, "dst": 3}.get(kind, 1)
         jobs.append((solver.tune_key(op, inst.n, inst.m, 1, True), call,
                      autotune.candidates(op, inst.n, inst.m, 1, solver.num_cu)))
     elif args.workload == "grad":
@@ -702,7 +714,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched_dense",
                     choices=["batched_dense", "pdct_hdr", "grad", "shared_dense", "phase", "pdct", "dense", "wht",
-                             "wht_hdr", "direct"])
+                             "wht_hdr", "dst", "direct"])
     ap.add_argument("--direct-n", type=int, default=4096, help="n of the direct workload (m = n/4)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--grad-n", type=int, default=1 << 18)

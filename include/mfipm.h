@@ -80,6 +80,9 @@ extern "C" {
 #define MFIPM_OP_WHT 2   /* rows of the orthonormal Walsh-Hadamard matrix H_n / sqrt(n) in
                             natural (Sylvester) order, another fast transform with orthonormal
                             rows (Section 1, Section 2); n a power of two, 64 <= n <= 2^20   */
+#define MFIPM_OP_PDST 3  /* rows of the orthonormal DST-II of length n, a further fast
+                            transform with orthonormal rows (Section 1, Section 2); n a power
+                            of two, 64 <= n <= 2^20                                          */
 
 typedef struct mfipm_handle mfipm_handle;
 
@@ -89,7 +92,9 @@ typedef struct mfipm_handle mfipm_handle;
  *        kept by A (borrowed); A*d = DCT-II_ortho(d)[rows],
  *        A^T*y = DCT-III_ortho(zero-fill(y)).
  * WHT  : rows as for PDCT, of W = H_n / sqrt(n); A*d = (W d)[rows],
- *        A^T*y = W zero-fill(y).                                                */
+ *        A^T*y = W zero-fill(y).
+ * PDST : rows as for PDCT, of the orthonormal DST-II S; A*d = (S d)[rows],
+ *        A^T*y = DST-III_ortho(zero-fill(y)).                                   */
 typedef struct {
   int32_t op;
   int64_t m, n;

@@ -183,6 +183,38 @@ class PartialWHTOperator:
         return scipy.linalg.hadamard(self.n)[self.rows] / math.sqrt(self.n)
 
 
+class PartialDSTOperator:
+    """A = R_m S: rows `rows` of the orthonormal DST-II of length n (another
+    fast transform with orthonormal rows); A^T y is the orthonormal DST-III
+    of the zero-filled y."""
+
+    def __init__(self, n: int, rows: np.ndarray):
+        self.n = int(n)
+        self.rows = np.asarray(rows, dtype=np.int64)
+        self.m = int(self.rows.shape[0])
+
+    def matvec(self, x):
+        return scipy.fft.dst(np.asarray(x, dtype=np.float64), type=2, norm="ortho")[self.rows]
+
+    def rmatvec(self, y):
+        full = np.zeros(self.n)
+        full[self.rows] = y
+        return scipy.fft.idst(full, type=2, norm="ortho")
+
+    def frob2(self) -> float:
+        return float(self.m)
+
+    def dense(self) -> np.ndarray:
+        """Explicit rows from the sine-sum definition (small n only):
+        S[k, j] = s_k sqrt(2/n) sin(pi (k + 1)(2 j + 1) / (2 n)), s_{n-1} = 1/sqrt(2)."""
+        n = self.n
+        k = self.rows[:, None].astype(np.float64)
+        j = np.arange(n, dtype=np.float64)[None, :]
+        S = math.sqrt(2.0 / n) * np.sin(math.pi * (k + 1.0) * (2.0 * j + 1.0) / (2.0 * n))
+        S[self.rows == n - 1, :] *= 1.0 / math.sqrt(2.0)
+        return S
+
+
 def make_operator(A=None, n=None, rows=None):
     if A is not None:
         return DenseOperator(A)

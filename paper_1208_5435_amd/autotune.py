@@ -84,7 +84,7 @@ def candidates(op_kind: int, n_max: int, m_max: int, batch: int, num_cu: int = 2
     """Candidate shapes for one call."""
     out = []
     if batch == 1:
-        if op_kind == 1:  # partial DCT
+        if op_kind in (1, 3):  # partial DCT or DST (one kernel)
             lh = int(math.log2(n_max)) - 1
             base = lh // 2
             tiles = sorted({t for t in (base - 2, base - 1, base, base + 1) if 1 <= t <= 9 and 3 <= lh - t <= 11})

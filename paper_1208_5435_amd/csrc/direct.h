@@ -30,6 +30,7 @@
 // LDS: two staged tiles (the factorisation uses the first as its tile and
 // the second for the pivots and a flag)
 #define DC_LDS_BYTES ((size_t)2 * DC_NB * DC_LD * sizeof(double))
+static_assert(4 * DC_NB + 1 <= DC_NB * DC_LD, "pivot scratch fits the second staging tile");
 
 typedef double dc_acc_t __attribute__((ext_vector_type(4)));
 
@@ -101,39 +102,54 @@ __device__ __forceinline__ int dc_col(int h) { return 32 * ((threadIdx.x >> 6) &
 
 // Cholesky of the SPD tile held in LDS (D, pitch DC_LD; lower triangle read)
 // by one workgroup: on return D's lower triangle holds L (tile = L L^T), Lg
-// (pitch ld) receives L and Lig (64 x 64 row-major) L^{-1}.  piv: 64 + 1
+// (pitch ld) receives L and Lig (64 x 64 row-major) L^{-1}.  piv: 4 x 64 + 1
 // doubles of LDS.  Returns nonzero in every thread if a pivot was not
 // positive.
 __device__ __noinline__ int dc_factor_tile(double* D, double* piv, double* Lg, long ld, double* Lig) {
-  int* bad = reinterpret_cast<int*>(piv + DC_NB);
+  double* col = piv;             // two buffers of the current pivot column
+  double* dg = piv + 2 * DC_NB;  // square roots of the pivots
+  double* rd = piv + 3 * DC_NB;  // their reciprocals
+  int* bad = reinterpret_cast<int*>(piv + 4 * DC_NB);
+  // Thread (i, p) keeps row i, columns p, p + 8, ..., p + 56 in registers
+  // and eliminates them with the unscaled pivot column:
+  // D[i][k] -= D[i][c] D[k][c] / D[c][c] for c < k <= i.
+  const int ri = threadIdx.x >> 3, rp = threadIdx.x & 7;
+  double a[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = D[ri * DC_LD + rp + 8 * q];
   if (threadIdx.x == 0) *bad = 0;
-  // right-looking elimination with the unscaled pivot column:
-  // D[i][k] -= D[i][c] D[k][c] / D[c][c] for c < k <= i
+#pragma unroll
   for (int c = 0; c < DC_NB; ++c) {
+    double* cb = col + (c & 1) * DC_NB;
+    if (rp == (c & 7) && ri >= c) cb[ri] = a[c >> 3];  // publish column c (final since step c - 1)
     __syncthreads();
-    const double dcc = D[c * DC_LD + c];
-    const double inv = 1.0 / dcc;
-    const int s = DC_NB - 1 - c;
-    for (int e = threadIdx.x; e < s * s; e += MF_THREADS) {
-      const int i = c + 1 + e / s, k = c + 1 + e % s;
-      if (k <= i) D[i * DC_LD + k] -= D[i * DC_LD + c] * D[k * DC_LD + c] * inv;
+    if (ri > c) {
+      const double f = cb[ri] / cb[c];
+#pragma unroll
+      for (int q = (c + 1) >> 3; q < 8; ++q) {
+        const int k = rp + 8 * q;
+        if (k > c && k <= ri) a[q] -= f * cb[k];
+      }
     }
   }
-  __syncthreads();
-  if (threadIdx.x < DC_NB) {
-    const double d = D[threadIdx.x * DC_LD + threadIdx.x];
+  // pivots, then L = D / sqrt(pivot) below the diagonal and sqrt(pivot) on it
+  if (rp == (ri & 7)) {
+    double d = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q == (ri >> 3)) d = a[q];
     if (!(d > 0.0)) *bad = 1;
-    piv[threadIdx.x] = sqrt(d);
+    const double sq = sqrt(d);
+    dg[ri] = sq;
+    rd[ri] = 1.0 / sq;
   }
   __syncthreads();
-  // L[i][k] = D[i][k] / sqrt(D[k][k]) below the diagonal, sqrt(D[k][k]) on it
-  for (int e = threadIdx.x; e < DC_NB * DC_NB; e += MF_THREADS) {
-    const int i = e >> 6, k = e & 63;
-    double v = 0.0;
-    if (k < i) v = D[i * DC_LD + k] / piv[k];
-    else if (k == i) v = piv[k];
-    D[i * DC_LD + k] = v;
-    Lg[(long)i * ld + k] = v;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k = rp + 8 * q;
+    const double v = k < ri ? a[q] * rd[k] : (k == ri ? dg[k] : 0.0);
+    D[ri * DC_LD + k] = v;
+    Lg[(long)ri * ld + k] = v;
   }
   __syncthreads();
   // L^{-1}: column j by the 8 lanes (j, p) of one wave; lane p keeps the
@@ -146,18 +162,22 @@ __device__ __noinline__ int dc_factor_tile(double* D, double* piv, double* Lg, l
     for (int q = 0; q < 8; ++q) xr[q] = 0.0;
 #pragma unroll
     for (int i = 0; i < DC_NB; ++i) {
-      double part = 0.0;
+      double part0 = 0.0, part1 = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (8 * q < i) {  // the slot may hold a k < i
           const int k = p + 8 * q;
-          if (k < i) part += D[i * DC_LD + k] * xr[q];
+          if (k < i) {
+            if (q & 1) part1 += D[i * DC_LD + k] * xr[q];
+            else part0 += D[i * DC_LD + k] * xr[q];
+          }
         }
       }
+      double part = part0 + part1;
       part += __shfl_xor(part, 1, 64);
       part += __shfl_xor(part, 2, 64);
       part += __shfl_xor(part, 4, 64);
-      const double xi = ((i == j ? 1.0 : 0.0) - part) / D[i * DC_LD + i];
+      const double xi = ((i == j ? 1.0 : 0.0) - part) * rd[i];
       if (p == (i & 7)) xr[i >> 3] = xi;
     }
 #pragma unroll

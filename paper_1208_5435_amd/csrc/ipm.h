@@ -79,6 +79,7 @@ struct KArgs {
   const double* A;
   const int* rows;
   int shared_op;
+  int op_flip;  // partial DST through the DCT kernel
   const double* b;
   double* x;
   double* state;
@@ -840,6 +841,7 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.tile = (cplx*)lds;
   op.a0 = sqrt(1.0 / (double)d.n);
   op.a1 = sqrt(2.0 / (double)d.n);
+  op.flip = a.op_flip;
 }
 
 __device__ __forceinline__ void make_op(OpWht& op, const KArgs& a, const InstDesc& d, const TeamWS& w, char* lds,

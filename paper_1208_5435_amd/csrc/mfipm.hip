@@ -83,6 +83,12 @@ static __device__ __align__(256) cplx tw_full[(1 << MFIPM_NOALLOC_TW_LO_BITS) +
 // ------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------
+// Kernel kinds: the four operator kinds, and the dense operator with the
+// direct (Cholesky) Newton solve.
+constexpr int kKindDirect = 4;
+constexpr int kKinds = 5;
+static_assert(kKindDirect == MFIPM_OP_PDST + 1 && kKinds == kKindDirect + 1, "kernel kinds follow the operator kinds");
+
 struct mfipm_handle {
   mfipm_params prm;
   hipStream_t stream;
@@ -92,9 +98,9 @@ struct mfipm_handle {
   int req_wg, req_team, req_tile;
   hipEvent_t ev0, ev1;
   double last_ms;
-  int occ[4][2][2];          // [kernel kind][bwd][reduced] max resident workgroups per CU
+  int occ[kKinds][2][2];     // [kernel kind][bwd][reduced] max resident workgroups per CU
   int occ_ls;                // the same for the lock-step kernel
-  size_t scratch_lane[4][2][2];  // [kernel kind][bwd][reduced] private bytes per lane
+  size_t scratch_lane[kKinds][2][2];  // [kernel kind][bwd][reduced] private bytes per lane
   // twiddle tables (device, owned by the handle), one per table resolution
   cplx* tw[32];
   // pinned host staging for the per-call uploads and read-backs
@@ -113,10 +119,9 @@ constexpr size_t kMaxDispatchScratch = (size_t)96 << 20;
 namespace {
 
 constexpr size_t kAlign = 256;
-// Kernel kinds: the three operator kinds, and the dense operator with the
-// direct (Cholesky) Newton solve.
-constexpr int kKindDirect = 3;
-constexpr int kKinds = 4;
+// the DCT-II and DST-II rows share one kernel (the DST through a sign flip
+// of the input and output and reversed coefficient indices)
+inline bool dct_family(int k) { return k == MFIPM_OP_PDCT || k == MFIPM_OP_PDST; }
 // Cap on the direct variant's per-team matrices (A^T A and M) of one call.
 constexpr size_t kDirectBudget = (size_t)32 << 30;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -227,7 +232,7 @@ GlobalLayout global_layout(int op_kind, long long n_max, int batch, int teams, c
   off += align_up((size_t)batch * (sizeof(InstDesc) + sizeof(int)));
   g.lo_bits = 0;
   g.hi_count = 0;
-  if (op_kind == MFIPM_OP_PDCT) {
+  if (dct_family(op_kind)) {
     const int lm = ilog2_host(n_max) + 2;  // table resolution 4 n_max
     g.lo_bits = (lm + 1) / 2;
     g.hi_count = 1LL << (lm - g.lo_bits);
@@ -368,7 +373,8 @@ struct Problem {
 int validate(const mfipm_handle* h, const Problem& P) {
   if (!h) return MFIPM_ERR_INVALID_ARG;
   if (P.batch < 1 || !P.n_off || !P.m_off) return MFIPM_ERR_INVALID_ARG;
-  if (P.op_kind != MFIPM_OP_DENSE && P.op_kind != MFIPM_OP_PDCT && P.op_kind != MFIPM_OP_WHT)
+  if (P.op_kind != MFIPM_OP_DENSE && P.op_kind != MFIPM_OP_PDCT && P.op_kind != MFIPM_OP_WHT &&
+      P.op_kind != MFIPM_OP_PDST)
     return MFIPM_ERR_INVALID_ARG;
   if (P.op_kind == MFIPM_OP_DENSE && !P.shared_op && !P.a_off) return MFIPM_ERR_INVALID_ARG;
   for (int i = 0; i < P.batch; ++i) {
@@ -498,7 +504,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   GlobalLayout gl = global_layout(kind, P.n_max, P.batch, teams_bound, tl);
   if (ws_bytes < gl.total) return noalloc ? MFIPM_ERR_TOO_LARGE : MFIPM_ERR_WORKSPACE_TOO_SMALL;
   int tw_log2n_max = ilog2_host(P.n_max);
-  if (noalloc && P.op_kind == MFIPM_OP_PDCT) {
+  if (noalloc && dct_family(P.op_kind)) {
     gl.lo_bits = MFIPM_NOALLOC_TW_LO_BITS;
     gl.hi_count = 1LL << (MFIPM_NOALLOC_TW_LOG2 - MFIPM_NOALLOC_TW_LO_BITS);
     tw_log2n_max = MFIPM_NOALLOC_TW_LOG2 - 2;
@@ -557,7 +563,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
     return code;
   };
   const cplx* tw = nullptr;
-  if (P.op_kind == MFIPM_OP_PDCT) {
+  if (dct_family(P.op_kind)) {
     tw = noalloc ? bk.tw_fixed : twiddle_tables(h, tw_log2n_max + 2, gl.lo_bits);
     if (!tw) return fail(MFIPM_ERR_HIP);
   }
@@ -582,6 +588,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   a.A = A;
   a.rows = rows;
   a.shared_op = P.shared_op;
+  a.op_flip = P.op_kind == MFIPM_OP_PDST ? 1 : 0;
   a.b = b;
   a.x = x;
   a.state = state;
@@ -869,7 +876,8 @@ double mfipm_last_kernel_ms(const mfipm_handle* h) { return h ? h->last_ms : -1.
 int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, int64_t max_m, int32_t batch,
                          size_t* bytes) {
   if (!h || !bytes || batch < 1 || max_n < 1 || max_m < 1) return MFIPM_ERR_INVALID_ARG;
-  if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT && op_kind != MFIPM_OP_WHT) return MFIPM_ERR_INVALID_ARG;
+  if (op_kind != MFIPM_OP_DENSE && op_kind != MFIPM_OP_PDCT && op_kind != MFIPM_OP_WHT && op_kind != MFIPM_OP_PDST)
+    return MFIPM_ERR_INVALID_ARG;
   size_t best = 0;
   for (int bwd = 0; bwd < 2; ++bwd)
     for (int red = 0; red < 2; ++red) {

@@ -199,6 +199,13 @@ struct OpPdct {
   unsigned char* msk;  // LDS: mask of the current pass-B item, rows (k1a, k1b)
   int cur_k1a;
   double a0, a1;
+  // Partial DST-II through the same transform: S d = P C D d with D =
+  // diag((-1)^j) and P the index reversal k -> n - 1 - k (the sine rows are
+  // the reversed cosine rows of the sign-alternated input; the orthonormal
+  // scalings match under the reversal).  flip = 1 applies D on the way in and
+  // out and reverses the coefficient indices.
+  int flip;
+  __device__ __forceinline__ double sgn(long i, double v) const { return (flip && (i & 1)) ? -v : v; }
 
   // mask value of coefficient owner (k, e), from the LDS copy of the item
   __device__ __forceinline__ double mval(int k, int e) const {
@@ -220,8 +227,10 @@ struct OpPdct {
   __device__ __forceinline__ int spos(int k, int e) const {
     return ((((k & (N1 - 1)) << l2) + (k >> l1)) << 1) + e;
   }
-  // spectral-layout position of DCT coefficient index kk in [0, n)
+  // spectral-layout position of DCT coefficient index kk in [0, n) (of the
+  // DST coefficient kk, which is DCT coefficient n - 1 - kk, when flip)
   __device__ __forceinline__ long coef_pos(long kk) const {
+    if (flip) kk = n - 1 - kk;
     if (kk == 0) return spos(0, 0);
     if (kk == H) return spos(0, 1);
     if (kk < H) return spos((int)kk, 0);
@@ -269,7 +278,7 @@ struct OpPdct {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int u = base + threadIdx.x + k * MF_THREADS;
-        if (u < units) td[slot[k]] = f.gather(idx[k], in[k]);
+        if (u < units) td[slot[k]] = sgn(idx[k], f.gather(idx[k], in[k]));
       }
     }
     __syncthreads();
@@ -328,8 +337,9 @@ struct OpPdct {
       for (int k = 0; k < U; ++k) {
         const int u = base + threadIdx.x + k * MF_THREADS;
         if (u < units) {
-          if constexpr (F::CHAIN) td[slot[k]] = f.scatter(idx[k], td[slot[k]], in[k]);
-          else f.scatter(idx[k], td[slot[k]], in[k]);
+          const double t = sgn(idx[k], td[slot[k]]);
+          if constexpr (F::CHAIN) td[slot[k]] = sgn(idx[k], f.scatter(idx[k], t, in[k]));
+          else f.scatter(idx[k], t, in[k]);
         }
       }
     }

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_PKG, "libmfipm.so")
 OP_DENSE = 0
 OP_PDCT = 1
 OP_WHT = 2
-TRANSFORMS = {"dct": OP_PDCT, "wht": OP_WHT}
+OP_PDST = 3
+TRANSFORMS = {"dct": OP_PDCT, "wht": OP_WHT, "dst": OP_PDST}
 
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "PCG_BREAKDOWN", 3: "NONFINITE", 4: "STEP_UNDERFLOW",
           5: "ABORTED", 6: "INPUT_CHECK", 7: "PCG_MAXITER"}
@@ -209,7 +210,9 @@ class Solver:
 
     def tune_key(self, op_kind, n_max, m_max, batch, shared, backward=False):
         from . import autotune
-        return autotune.make_key(self.arch, op_kind, n_max, m_max, batch, shared, backward)
+        # the DST rows run on the DCT kernel: they share its tuned shapes
+        kind = OP_PDCT if op_kind == OP_PDST else op_kind
+        return autotune.make_key(self.arch, kind, n_max, m_max, batch, shared, backward)
 
     def _apply_shape(self, op_kind, n_max, m_max, batch, shared, backward=False):
         from . import autotune
@@ -235,7 +238,7 @@ class Solver:
     def solve(self, b, tau, A=None, rows=None, n=None, want_state=True, transform="dct") -> Result:
         """Solves min tau||x||_1 + 1/2||Ax-b||^2 with a dense A (m x n, float64,
         contiguous) or rows of a fast transform of length n (rows: int32 sorted
-        distinct; transform "dct" or "wht")."""
+        distinct; transform "dct", "dst" or "wht")."""
         torch = self.torch
         b = _dev(b, self.device, torch.float64)
         if A is not None:

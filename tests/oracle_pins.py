@@ -264,3 +264,23 @@ def pin_wht_definition(n, m, seed):
     e3 = np.linalg.norm(op.matvec(op.rmatvec(y)) - y) / np.linalg.norm(y)
     e4 = np.linalg.norm(op.dense() @ x - op.matvec(x)) / np.linalg.norm(ref)
     return max(e1, e2, e3, e4)
+
+
+def pin_dst_definition(n, m, seed):
+    """Partial DST operator against its entries written out from the sine sum
+    S[k, j] = c_k sin(pi (k + 1)(2 j + 1) / (2 n)), c_k = sqrt(2/n) (sqrt(1/n)
+    for k = n - 1), with the sum taken term by term here; plus the adjoint
+    identity and A A^T = I.  Returns the largest error."""
+    rng = rng_for(seed)
+    rows = np.sort(rng.choice(n, m, replace=False))
+    op = R.PartialDSTOperator(n, rows)
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    ref = np.zeros(m)
+    for a, k in enumerate(rows):
+        c = math.sqrt((1.0 if k == n - 1 else 2.0) / n)
+        ref[a] = c * sum(x[j] * math.sin(math.pi * (k + 1) * (2 * j + 1) / (2 * n)) for j in range(n))
+    e1 = np.linalg.norm(op.matvec(x) - ref) / np.linalg.norm(ref)
+    e2 = abs(op.matvec(x) @ y - x @ op.rmatvec(y)) / (np.linalg.norm(x) * np.linalg.norm(y))
+    e3 = np.linalg.norm(op.matvec(op.rmatvec(y)) - y) / np.linalg.norm(y)
+    return max(e1, e2, e3)

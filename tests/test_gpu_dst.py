@@ -1,0 +1,138 @@
+"""Partial DST operator (GPU): rows of the orthonormal DST-II, computed by
+the DCT kernel with a sign flip of the input and output and reversed
+coefficient indices, against the oracle's PartialDSTOperator (scipy's
+DST-II/III): single solves over the range of lengths, the n = 2^16 workload
+at the strict bar, an uneven batch, shared rows with the adjoint, and the
+no-allocation entry point."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mfipm_ref as R
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver(gpu_lib):
+    from paper_1208_5435_amd import Solver
+    s = Solver()
+    yield s
+    s.close()
+
+
+def _offsets(sizes):
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def _resolve(solver, inst, b=None, tau=None):
+    return U.resolver(solver, b=inst.b if b is None else b, tau=inst.tau if tau is None else tau, rows=inst.rows,
+                      n=inst.n, transform="dst")
+
+
+@pytest.mark.parametrize("n,m,k,seed", [(64, 16, 2, 1), (128, 40, 3, 2), (1024, 256, 10, 3), (1024, 1000, 20, 4),
+                                        (4096, 1023, 40, 5), (8192, 2048, 81, 6)])
+def test_dst_small(solver, n, m, k, seed):
+    say(f"dst n={n} m={m} seed={seed}")
+    inst = W.dct_instance(n, m, k, seed=seed, amp="normal", sigma=1e-2, c_tau=1e-2, transform="dst")
+    res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=n, transform="dst")
+    U.check_against_oracle(R.PartialDSTOperator(n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(), res.infos[0],
+                           res.state.cpu().numpy(), label=f"dst{n}/{m}", resolve=_resolve(solver, inst))
+
+
+def test_dst_2p16(solver):
+    say("dst n=2^16 workload")
+    inst = W.config_dst()
+    res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n, transform="dst")
+    ref = U.check_against_oracle(R.PartialDSTOperator(inst.n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(),
+                                 res.infos[0], res.state.cpu().numpy(), label="dst 2^16", strict=True)
+    say("  gpu", res.infos[0], "oracle", ref.ipm_iters, ref.pcg_iters, "ms", res.kernel_ms)
+
+
+def test_dst_all_rows_soft_threshold(solver):
+    """All rows kept: A is the orthogonal DST-II matrix, the minimiser is the
+    soft threshold of S^T b, written here from the sine-sum entries."""
+    n = 256
+    rng = np.random.default_rng(np.random.PCG64(33))
+    b = rng.standard_normal(n)
+    rows = np.arange(n, dtype=np.int32)
+    solver.set_params(tol=1e-12)
+    try:
+        res = solver.solve(b, 0.5, rows=rows, n=n, transform="dst")
+    finally:
+        solver.set_params(tol=1e-8)
+    k = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    S = np.sqrt(2.0 / n) * np.sin(np.pi * (k + 1) * (2 * j + 1) / (2 * n))
+    S[n - 1] /= np.sqrt(2.0)
+    c = S.T @ b
+    x_cf = np.sign(c) * np.maximum(np.abs(c) - 0.5, 0.0)
+    assert res.infos[0]["status"] == 0
+    assert U.rel(res.x.cpu().numpy(), x_cf) <= 1e-7
+
+
+def test_dst_batched_uneven(solver):
+    ns = [64, 256, 1024, 4096, 512]
+    insts = [W.dct_instance(n, n // 4, max(1, n // 100), seed=800 + i, transform="dst") for i, n in enumerate(ns)]
+    say("batched dst", ns)
+    n_off = _offsets([i.n for i in insts])
+    m_off = _offsets([i.m for i in insts])
+    rows = np.concatenate([i.rows for i in insts])
+    b = np.concatenate([i.b for i in insts])
+    res = solver.solve_batched(b, [i.tau for i in insts], n_off, m_off, rows=rows, transform="dst")
+    x = res.x.cpu().numpy()
+    st = res.state.cpu().numpy()
+    for j, inst in enumerate(insts):
+        U.check_against_oracle(R.PartialDSTOperator(inst.n, inst.rows), inst.b, inst.tau, x[n_off[j]:n_off[j + 1]],
+                               res.infos[j], st[4 * n_off[j]:4 * n_off[j + 1]], label=f"batch dst {j}",
+                               resolve=_resolve(solver, inst))
+
+
+def test_dst_shared_and_adjoint(solver):
+    inst = W.config_dct_batch(n=4096, batch=4, transform="dst")
+    B, m = inst.b.shape
+    n = inst.n
+    n_off = np.arange(B + 1, dtype=np.int64) * n
+    m_off = np.arange(B + 1, dtype=np.int64) * m
+    res = solver.solve_batched(inst.b.reshape(-1), inst.tau, n_off, m_off, rows=inst.rows, shared_op=True,
+                               transform="dst")
+    x = res.x.cpu().numpy()
+    st = res.state.cpu().numpy()
+    gx = x - inst.x_true.reshape(-1)
+    gb, gt, binf = solver.backward(res.state, gx, n_off, m_off, rows=inst.rows, shared_op=True, transform="dst")
+    op = R.PartialDSTOperator(n, inst.rows)
+    gb = gb.cpu().numpy().reshape(B, m)
+    gt = gt.cpu().numpy()
+    for j in range(B):
+        sl = slice(j * n, (j + 1) * n)
+        U.check_against_oracle(op, inst.b[j], inst.tau[j], x[sl], res.infos[j], st[4 * n * j:4 * n * (j + 1)],
+                               label=f"dst shared {j}",
+                               resolve=U.resolver(solver, b=inst.b[j], tau=float(inst.tau[j]), rows=inst.rows, n=n,
+                                                  transform="dst"))
+        assert binf[j]["status"] == 0, binf[j]
+        z, s = U.zs_from_state(st[4 * n * j:4 * n * (j + 1)], n)
+        ref = R.backward(op, z, s, gx[sl])
+        assert U.rel(gb[j], ref.grad_b) <= 1e-8, j
+        assert abs(gt[j] - ref.grad_tau) <= 1e-8 * abs(ref.grad_tau), j
+
+
+def test_dst_noalloc_matches_solve(solver):
+    import torch
+    inst = W.dct_instance(4096, 1024, 40, seed=43, transform="dst")
+    ref = solver.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n, transform="dst")
+    dev = solver.device
+    b = torch.as_tensor(inst.b, dtype=torch.float64, device=dev)
+    rows = torch.as_tensor(inst.rows, dtype=torch.int32, device=dev)
+    x = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    info = solver.solve_noalloc(b, inst.tau, x, rows=rows, n=inst.n, transform="dst")
+    assert info["status"] == ref.infos[0]["status"] == 0
+    assert abs(info["ipm_iters"] - ref.infos[0]["ipm_iters"]) <= U.ITER_SLACK
+    assert U.rel(x.cpu().numpy(), ref.x.cpu().numpy()) <= U.X_REL

@@ -281,3 +281,24 @@ def test_wht_newton_blocks_and_theorem(kind):
     n = 32
     op = R.PartialWHTOperator(n, np.sort(rng.choice(n, 8, replace=False)))
     assert PIN.pin_newton_blocks(op, seed=4) <= 1e-7
+
+
+@pytest.mark.parametrize("n,m", [(64, 16), (128, 100)])
+def test_dst_definition(n, m):
+    assert PIN.pin_dst_definition(n, m, seed=n + 5) <= 1e-12
+
+
+def test_dst_full_soft_threshold():
+    """All rows of the orthonormal DST-II: x* = soft(S^T b, tau)."""
+    rng = PIN.rng_for(63)
+    n = 128
+    op = R.PartialDSTOperator(n, np.arange(n))
+    b = rng.standard_normal(n)
+    assert PIN.pin_orthonormal_soft_threshold(op, b, 0.5) <= 1e-7
+
+
+def test_dst_newton_blocks_and_theorem():
+    rng = PIN.rng_for(64)
+    n = 32
+    op = R.PartialDSTOperator(n, np.sort(rng.choice(n, 8, replace=False)))
+    assert PIN.pin_newton_blocks(op, seed=6) <= 1e-7

@@ -230,3 +230,14 @@ def test_wht_ordering_slip_caught(monkeypatch):
         return y
     monkeypatch.setattr(R, "fwht", bad_fwht)
     assert PIN.pin_wht_definition(64, 16, seed=67) > 1e-3
+
+
+def test_dst_type_slip_caught(monkeypatch):
+    """A DST-I in place of the DST-II is caught by the sine-sum pin."""
+    real_dst = R.scipy.fft.dst
+
+    def bad_dst(x, type=2, norm=None):
+        return real_dst(x, type=1, norm=norm)
+
+    monkeypatch.setattr(R.scipy.fft, "dst", bad_dst)
+    assert PIN.pin_dst_definition(64, 16, seed=69) > 1e-3

@@ -16,6 +16,7 @@ Operators:
     R_m keeps m distinct rows drawn uniformly without replacement, sorted
     ascending (paper, Section 2 orthonormal rows, eq. (eq:orthonormality), and
     Section 5.8 phase-transition setup "normalized DCT");
+  * partial DST: A = R_m S with S the orthonormal DST-II, rows as for the DCT;
   * partial Walsh-Hadamard: A = R_m W, W = H_n / sqrt(n) with H_n the
     Sylvester-ordered Hadamard matrix, rows drawn as for the DCT (another fast
     orthonormal transform, paper Sections 1-2).
@@ -38,6 +39,7 @@ __all__ = [
     "batched_dense_sizes", "batched_dense_instance", "config_dct_batch",
     "dct_apply", "dct_apply_t", "SharedDenseInstance", "config_shared_dense",
     "wht_apply", "wht_apply_t", "config_wht", "config_wht_hdr", "direct_scaling_instance",
+    "dst_apply", "dst_apply_t", "config_dst",
     "DIRECT_SCALING_NS",
 ]
 
@@ -78,7 +80,19 @@ def wht_apply_t(rows: np.ndarray, n: int, y: np.ndarray) -> np.ndarray:
     return _hadamard_unnormalised(full) / np.sqrt(n)
 
 
-_APPLY = {"dct": (dct_apply, dct_apply_t), "wht": (wht_apply, wht_apply_t)}
+def dst_apply(rows: np.ndarray, n: int, x: np.ndarray) -> np.ndarray:
+    """Rows `rows` of the orthonormal DST-II of x (input synthesis only)."""
+    return scipy.fft.dst(np.asarray(x, np.float64), type=2, norm="ortho")[rows]
+
+
+def dst_apply_t(rows: np.ndarray, n: int, y: np.ndarray) -> np.ndarray:
+    """Transpose of dst_apply: zero-fill to length n, orthonormal DST-III."""
+    full = np.zeros(n, np.float64)
+    full[rows] = y
+    return scipy.fft.idst(full, type=2, norm="ortho")
+
+
+_APPLY = {"dct": (dct_apply, dct_apply_t), "wht": (wht_apply, wht_apply_t), "dst": (dst_apply, dst_apply_t)}
 
 
 def _sparse_signal(rng: np.random.Generator, n: int, k: int, amp: str) -> np.ndarray:
@@ -175,6 +189,12 @@ def config_pdct_hdr(n: int = 1 << 20) -> DCTInstance:
     """Partial DCT n=2^20, m=n/4, k=floor(n/200) +-10^U(0,3), noise 1e-3, c_tau 1e-3."""
     return dct_instance(n, n // 4, n // 200, seed=120803, amp="hdr", sigma=1e-3, c_tau=1e-3,
                         label=f"pdct_hdr_n{n}")
+
+
+def config_dst(n: int = 1 << 16) -> DCTInstance:
+    """Partial DST n=2^16 with the partial-DCT n=2^16 recipe."""
+    return dct_instance(n, n // 4, n // 100, seed=120812, amp="normal", sigma=1e-2, c_tau=1e-2,
+                        label=f"dst_n{n}", transform="dst")
 
 
 def config_wht(n: int = 1 << 16) -> DCTInstance:
