@@ -327,7 +327,11 @@ __device__ __noinline__ int direct_factor(Ctx& cx, OpDenseDirect& op, const doub
     // rank 0, which then factorises it
     const int S = T - 1 - j;
     const int nupd = S * (S + 1) / 2;
-    for (int u = cx.t.rank; u < nupd; u += cx.t.size) {
+    // rank 0 takes only the diagonal tile (it factorises it afterwards); the
+    // other tiles go to the other ranks
+    const int ustart = cx.t.size == 1 ? 0 : (cx.t.rank == 0 ? 0 : cx.t.rank);
+    const int ustep = cx.t.size == 1 ? 1 : (cx.t.rank == 0 ? nupd : cx.t.size - 1);
+    for (int u = ustart; u < nupd; u += ustep) {
       int ii, kk;
       dc_tri_index(u, ii, kk);
       const int i = j + 1 + ii, k = j + 1 + kk;

@@ -305,10 +305,9 @@ class Solver:
         N = int(n_off[-1])
         x = torch.empty(N, dtype=torch.float64, device=self.device)
         state = torch.empty(4 * N, dtype=torch.float64, device=self.device) if want_state else None
-        ns = np.diff(n_off)
-        ms = np.diff(m_off)
-        self._apply_shape(kind, int(ns.max()), int(ms.max()), batch, shared_op)
-        ws, nb = self.workspace(kind, int(ns.max()), int(ms.max()), batch)
+        nmax, mmax = _max_sizes(n_off, m_off)
+        self._apply_shape(kind, nmax, mmax, batch, shared_op)
+        ws, nb = self.workspace(kind, nmax, mmax, batch)
         infos = (Info * batch)()
         rc = self.lib.mfipm_solve_batched(
             self.h, batch, n_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -336,10 +335,9 @@ class Solver:
         rows = _dev(rows, self.device, torch.int32) if rows is not None else None
         grad_b = torch.empty(int(m_off[-1]), dtype=torch.float64, device=self.device)
         grad_tau = torch.empty(batch, dtype=torch.float64, device=self.device)
-        ns = np.diff(n_off)
-        ms = np.diff(m_off)
-        self._apply_shape(kind, int(ns.max()), int(ms.max()), batch, shared_op, backward=True)
-        ws, nb = self.workspace(kind, int(ns.max()), int(ms.max()), batch)
+        nmax, mmax = _max_sizes(n_off, m_off)
+        self._apply_shape(kind, nmax, mmax, batch, shared_op, backward=True)
+        ws, nb = self.workspace(kind, nmax, mmax, batch)
         infos = (Info * batch)()
         rc = self.lib.mfipm_backward(
             self.h, batch, n_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -348,6 +346,14 @@ class Solver:
             1 if shared_op else 0, _ptr(state), _ptr(grad_x), _ptr(grad_b), _ptr(grad_tau), _ptr(ws), nb, infos)
         _check("mfipm_backward", rc)
         return grad_b, grad_tau, [i.as_dict() for i in infos]
+
+
+def _max_sizes(n_off, m_off):
+    """Largest n and m of a batch (1, 1 for an empty one, which the library
+    then rejects)."""
+    ns = np.diff(n_off)
+    ms = np.diff(m_off)
+    return (int(ns.max()) if ns.size else 1), (int(ms.max()) if ms.size else 1)
 
 
 def _transform(name):
