@@ -189,6 +189,14 @@ __device__ __forceinline__ int team_barrier(Team& t) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   t.gen += 1;
+  if (t.size == 1) {
+    // A one-workgroup team has nothing to publish: its waves share the CU's
+    // L1, which is coherent within the workgroup (no agent-scope release and
+    // acquire, so no write-back of the XCD's L2 at every barrier).
+    if (threadIdx.x == 0) s_abort = ld_flag(t.abort_flag);
+    __syncthreads();
+    return s_abort;
+  }
   if (threadIdx.x == 0) {
     int ab = ld_flag(t.abort_flag);
     unsigned long long* rel = t.ctl;

@@ -236,7 +236,7 @@ def test_autograd_batched_shared_dct(solver):
     assert well_posed >= 2
 
 
-@pytest.mark.parametrize("team,total", [(3, 0), (5, 40), (7, 21), (12, 0)])
+@pytest.mark.parametrize("team,total", [(1, 0), (1, 5), (3, 0), (5, 40), (7, 21), (12, 0)])
 def test_batched_odd_team_sizes(solver, team, total):
     """Teams whose workgroups spread unevenly over the XCDs (the team barrier
     groups a team's workgroups by the XCD they run on): every instance of an
