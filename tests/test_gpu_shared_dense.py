@@ -40,7 +40,7 @@ def _run(solver, inst, team=0):
         solver.set_launch(0, 0, 0)
 
 
-@pytest.mark.parametrize("m,n,B", [(128, 512, 24), (100, 300, 9), (64, 256, 70)])
+@pytest.mark.parametrize("m,n,B", [(128, 512, 24), (100, 300, 9), (64, 256, 70), (101, 300, 9)])
 def test_lockstep_vs_oracle(solver, m, n, B):
     """Ragged shapes: m, n not multiples of the 64 x 64 tiles or the 32-wide
     K chunks; B not a multiple of the 64-signal column groups."""
