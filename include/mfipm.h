@@ -189,9 +189,11 @@ int mfipm_workspace_size(const mfipm_handle* h, int32_t op_kind, int64_t max_n, 
  * (output); state: 4n doubles (output, may be NULL) -- the final (z, s),
  * which mfipm_backward needs; ws/ws_bytes: workspace of at least
  * mfipm_workspace_size(h, op->op, op->n, op->m, 1) bytes; info: host.
- * Errors: INVALID_ARG (NULL pointers, m < 1, m > n, tau <= 0 or not finite,
- * PDCT n not a power of two in [64, 2^20]); WORKSPACE_TOO_SMALL;
- * DEVICE_CHECK (rows not sorted/distinct/in range); HIP.                     */
+ * Errors: INVALID_ARG (NULL pointers, m < 1, tau <= 0 or not finite; for
+ * PDCT, PDST and WHT: n not a power of two in [64, 2^20] or m > n; with
+ * params.direct: an operator other than DENSE or n > 8192);
+ * WORKSPACE_TOO_SMALL; DEVICE_CHECK (rows not sorted/distinct/in range);
+ * HIP.                                                                      */
 int mfipm_solve(mfipm_handle* h, const mfipm_operator* op, const double* b, double tau,
                 double* x, double* state, void* ws, size_t ws_bytes, mfipm_info* info);
 

@@ -254,15 +254,14 @@ __device__ __noinline__ int direct_setup(Ctx& cx, OpDenseDirect& op, int* err) {
     int I, J;
     dc_tri_index(u, I, J);
     dc_acc_t acc[2] = {dc_acc_t{0, 0, 0, 0}, dc_acc_t{0, 0, 0, 0}};
+    // columns of A in the tile (I, J < T, so at least one each; the padding reads zeros)
     const int ci = (int)min((long)DC_NB, op.n - (long)I * DC_NB);
     const int cj = (int)min((long)DC_NB, op.n - (long)J * DC_NB);
     for (long r0 = 0; r0 < op.m; r0 += DC_NB) {
       const int rows = (int)min((long)DC_NB, op.m - r0);
       // X[i][k] = A[r0 + k][64 I + i], Y[j][k] = A[r0 + k][64 J + j]
-      if (ci > 0) dc_stage(op.sX, op.A + r0 * op.lda + (long)I * DC_NB, op.lda, rows, ci);
-      else dc_stage(op.sX, op.A, op.lda, 0, 0);
-      if (cj > 0) dc_stage(op.sY, op.A + r0 * op.lda + (long)J * DC_NB, op.lda, rows, cj);
-      else dc_stage(op.sY, op.A, op.lda, 0, 0);
+      dc_stage(op.sX, op.A + r0 * op.lda + (long)I * DC_NB, op.lda, rows, ci);
+      dc_stage(op.sY, op.A + r0 * op.lda + (long)J * DC_NB, op.lda, rows, cj);
       __syncthreads();
       dc_mfma(op.sX, op.sY, acc);
       __syncthreads();

@@ -1,6 +1,8 @@
 // Device-side driver of the single-corrector primal-dual matrix-free IPM
 // (Section 5.1 algorithm) and of its PCG inner solver (Section 4), written
-// once over an operator policy (OpDense / OpPdct).  Per-index data are
+// once over an operator policy (OpDense; OpPdct, which also serves the DST
+// rows; OpWht; OpDenseDirect, whose Newton solves are the Cholesky ones of
+// direct.h instead of the PCG).  Per-index data are
 // interleaved (u_i, v_i) pairs (double2) so that the 2x2 block structure of
 // H and P (Section 4, eqs. (eq:ne2_H), (eq:ne2_P)) is local to one index.
 //
