@@ -97,6 +97,7 @@ struct KArgs {
   int tw_lo_bits;
   int tw_log2n_max;
   int team_size;
+  int num_teams;
   int tile_param;
   unsigned long long spin_ticks;
 };

@@ -35,8 +35,11 @@ __global__ void __launch_bounds__(MF_THREADS) k_mfipm(KArgs a) {
   Ctx cx;
   cx.red = red;
   cx.t.size = a.team_size;
-  cx.t.id = blockIdx.x / a.team_size;
-  cx.t.rank = blockIdx.x % a.team_size;
+  // Teams are interleaved over the grid (workgroup b belongs to team
+  // b mod num_teams): the workgroups are dealt to the XCDs round robin, so
+  // with a multiple of 8 teams each team runs on one XCD and shares its L2.
+  cx.t.id = blockIdx.x % a.num_teams;
+  cx.t.rank = blockIdx.x / a.num_teams;
   cx.t.gen = 0;
   cx.t.abort_flag = a.abort_flag;
   cx.t.spin_ticks = a.spin_ticks;
@@ -604,6 +607,7 @@ int launch(mfipm_handle* h, const Problem& P, int bwd, const double* A, const in
   a.tw_lo_bits = gl.lo_bits;
   a.tw_log2n_max = tw_log2n_max;
   a.team_size = team_size;
+  a.num_teams = num_teams;
   a.tile_param = h->req_tile;
   a.spin_ticks = (unsigned long long)h->wall_khz * 1000ull * 5ull;  // 5 s per wait
 
