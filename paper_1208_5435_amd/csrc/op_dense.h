@@ -34,6 +34,13 @@
 // keeping it.  The caller swaps Dxc and Dxn after a kept residual.
 enum { DB_HAPPLY = 0, DB_RESID = 1, DB_OUT = 2, DB_RESID_STEP = 3, DB_RESID_TRIAL = 4 };
 
+// 16-byte non-temporal load of a pair of doubles
+typedef double dn_pair_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream2(const double2* p) {
+  const dn_pair_t v = __builtin_nontemporal_load(reinterpret_cast<const dn_pair_t*>(p));
+  return make_double2(v.x, v.y);
+}
+
 struct OpDense {
   long n;
   long m;
@@ -133,7 +140,9 @@ struct OpDense {
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
           const long p = tid + (long)k * MF_THREADS;
-          a[r][k] = (rv && p < npair) ? row[p] : make_double2(0.0, 0.0);
+          // A is streamed once per operator application: a non-temporal
+          // load keeps it from displacing the reused vectors in the caches
+          a[r][k] = (rv && p < npair) ? ld_stream2(row + p) : make_double2(0.0, 0.0);
         }
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
