@@ -109,3 +109,19 @@ def test_direct_argument_checks(solver):
     with pytest.raises(MfipmError) as e:
         solver.solve(rng.standard_normal(8), 0.1, A=A)
     assert e.value.code == -1
+
+
+def test_direct_noalloc_matches_solve(solver):
+    """The no-allocation entry point with exact Newton directions: the
+    factorisation's matrices fit the static scratch at this size."""
+    import torch
+    inst = W.direct_scaling_instance(512)
+    ref = solver.solve(inst.b, inst.tau, A=inst.A)
+    dev = solver.device
+    A = torch.as_tensor(inst.A, dtype=torch.float64, device=dev)
+    b = torch.as_tensor(inst.b, dtype=torch.float64, device=dev)
+    x = torch.empty(inst.n, dtype=torch.float64, device=dev)
+    info = solver.solve_noalloc(b, inst.tau, x, A=A)
+    assert info["status"] == ref.infos[0]["status"] == 0
+    assert abs(info["ipm_iters"] - ref.infos[0]["ipm_iters"]) <= U.ITER_SLACK
+    assert U.rel(x.cpu().numpy(), ref.x.cpu().numpy()) <= U.X_REL
