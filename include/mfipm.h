@@ -25,6 +25,10 @@
  *   - Work is ordered on the stream given to mfipm_create (a hipStream_t
  *     passed as void*; NULL = the default stream).  solve/backward calls
  *     return after the work has finished and `info` is filled.
+ *   - A handle is not thread-safe: calls on one handle must not overlap
+ *     (it reuses its pinned staging buffer and events between calls); use
+ *     one handle per host thread.  Handles on one device share nothing but
+ *     the static scratch of mfipm_solve_noalloc, whose calls are serialised.
  *   - Return value: 0 = OK; negative = error, nothing was computed
  *     (MFIPM_ERR_*).  No entry point aborts, throws or exits.
  *   - The solver outcome of each instance is reported in mfipm_info.status
