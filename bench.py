@@ -142,11 +142,44 @@ def _line(value, unit, args, ms_step, config, roofline, higher=True):
             "config": config, "roofline": roofline}
 
 
+_COPY_GBS = None
+_COPY_PROBE = True  # off in counter runs, whose only copy must be the calibration copy
+
+
+def measured_copy_gbs():
+    """Device-to-device copy rate of this GPU (1 GiB read + 1 GiB written per
+    copy, best of five after a warm-up, HIP events): the achievable streaming
+    bandwidth the algorithmic GB/s is also compared with."""
+    global _COPY_GBS
+    if not _COPY_PROBE:
+        return None
+    if _COPY_GBS is None:
+        import torch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        best = None
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        _COPY_GBS = 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+        del src, dst
+    return _COPY_GBS
+
+
 def _hbm_roofline(ab, kernel_ms, kernel, workload):
     achieved = ab / (kernel_ms * 1e-3) / 1e9
+    copy = measured_copy_gbs()
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
-            "kernel": kernel, "alg_bytes_per_launch": ab}
+            "kernel": kernel, "alg_bytes_per_launch": ab, "copy_gbs": round(copy, 1) if copy else None,
+            "frac_of_copy": round(achieved / copy, 4) if copy else None}
 
 
 def _params(args):
@@ -738,6 +771,8 @@ def main():
                          "(needs --copy-calib-mb as used in those runs); runs nothing on the GPU")
     ap.add_argument("--traffic-key", default=None, help="workload key for --traffic-from")
     args = ap.parse_args()
+    global _COPY_PROBE
+    _COPY_PROBE = args.copy_calib_mb <= 0
     if args.traffic_from:
         write_traffic(args.traffic_key or args.workload, args.traffic_from[0], args.traffic_from[1],
                       args.copy_calib_mb)
