@@ -1,8 +1,8 @@
 """Partial DST operator (GPU): rows of the orthonormal DST-II, computed by
 the DCT kernel with a sign flip of the input and output and reversed
 coefficient indices, against the oracle's PartialDSTOperator (scipy's
-DST-II/III): single solves over the range of lengths, the n = 2^16 workload
-at the strict bar, an uneven batch, shared rows with the adjoint, and the
+DST-II/III): single solves over the range of lengths, the n = 2^16 workload and
+n = 2^20 at the strict bar, an uneven batch, shared rows with the adjoint, and the
 no-allocation entry point."""
 import sys
 
@@ -54,6 +54,17 @@ def test_dst_2p16(solver):
     res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=inst.n, transform="dst")
     ref = U.check_against_oracle(R.PartialDSTOperator(inst.n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(),
                                  res.infos[0], res.state.cpu().numpy(), label="dst 2^16", strict=True)
+    say("  gpu", res.infos[0], "oracle", ref.ipm_iters, ref.pcg_iters, "ms", res.kernel_ms)
+
+
+def test_dst_2p20_hdr(solver):
+    """The largest length, with the high-dynamic-range recipe, at the strict bar."""
+    say("dst n=2^20 high-dynamic-range")
+    n = 1 << 20
+    inst = W.dct_instance(n, n // 4, n // 200, seed=120813, amp="hdr", sigma=1e-3, c_tau=1e-3, transform="dst")
+    res = solver.solve(inst.b, inst.tau, rows=inst.rows, n=n, transform="dst")
+    ref = U.check_against_oracle(R.PartialDSTOperator(n, inst.rows), inst.b, inst.tau, res.x.cpu().numpy(),
+                                 res.infos[0], res.state.cpu().numpy(), label="dst 2^20 hdr", strict=True)
     say("  gpu", res.infos[0], "oracle", ref.ipm_iters, ref.pcg_iters, "ms", res.kernel_ms)
 
 
