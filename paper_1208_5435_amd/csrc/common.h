@@ -266,7 +266,10 @@ __device__ __forceinline__ void wg_reduce(const int* kinds, double (&v)[K], doub
 }
 
 // Reduce per-item partials part[item * MF_MAXK + j] over items [0, nitems) in
-// a fixed order; every thread of the workgroup receives the K results.
+// a fixed order; every thread of the workgroup receives the K results.  Lane
+// l folds items l, l + 64, l + 128, ... in that order; the loads of four such
+// items are issued together before they are folded, so that a team of a few
+// hundred workgroups pays one memory round trip here instead of one per item.
 template <int K>
 __device__ __forceinline__ void reduce_items(const int* kinds, const double* part, int nitems, double (&res)[K],
                                     double* lds_scratch) {
@@ -275,9 +278,22 @@ __device__ __forceinline__ void reduce_items(const int* kinds, const double* par
     double a[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) a[j] = rid(kinds[j]);
-    for (int it = lane; it < nitems; it += 64) {
+    constexpr int RU = 4;
+    for (int it0 = lane; it0 < nitems; it0 += 64 * RU) {
+      double v[RU][K];
 #pragma unroll
-      for (int j = 0; j < K; ++j) a[j] = rop(kinds[j], a[j], part[(long)it * MF_MAXK + j]);
+      for (int u = 0; u < RU; ++u) {
+        const int it = it0 + 64 * u;
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[u][j] = it < nitems ? part[(long)it * MF_MAXK + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        if (it0 + 64 * u < nitems) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) a[j] = rop(kinds[j], a[j], v[u][j]);
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) a[j] = wave_reduce(kinds[j], a[j]);

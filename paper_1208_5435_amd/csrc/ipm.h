@@ -835,7 +835,7 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.mask = w.mask;
   op.bt = w.bt;
   op.XS = w.XS;
-  op.tw.lo = (const cplx*)lds + PD_TILE_CPLX;
+  op.tw.lo = (const cplx*)lds + PD_TILE_LDS;
   op.tw.hi = op.tw.lo + (1 << a.tw_lo_bits);
   op.tw.lo_bits = a.tw_lo_bits;
   op.msk = (unsigned char*)(op.tw.hi + (1 << (a.tw_log2n_max + 2 - a.tw_lo_bits)));

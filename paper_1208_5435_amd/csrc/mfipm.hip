@@ -291,7 +291,7 @@ size_t dyn_lds(int op_kind, int lo_bits = -1, long long hi_count = 0) {
     lo_bits = (lm + 1) / 2;
     hi_count = 1LL << (lm - lo_bits);
   }
-  return (size_t)PD_TILE_CPLX * sizeof(cplx) + (((size_t)1 << lo_bits) + (size_t)hi_count) * sizeof(cplx) +
+  return (size_t)PD_TILE_LDS * sizeof(cplx) + (((size_t)1 << lo_bits) + (size_t)hi_count) * sizeof(cplx) +
          PD_MASK_BYTES;
 }
 

@@ -32,6 +32,14 @@
 
 #define PD_TILE_CPLX 4096  // LDS tile: 4096 complex doubles = 64 KiB
 #define PD_EPT (PD_TILE_CPLX / MF_THREADS)  // tile elements per thread
+// Tile element a lives at LDS slot a + a / 16: one unused slot after every 16
+// elements.  The early Stockham passes write with a stride of R elements
+// (R x 16 bytes); unpadded, those lanes fall on the same few LDS banks.
+#define PD_PAD_SH 4
+#define PD_TILE_LDS (PD_TILE_CPLX + (PD_TILE_CPLX >> PD_PAD_SH))  // LDS slots of the padded tile
+__device__ __forceinline__ int tpad(int a) { return a + (a >> PD_PAD_SH); }
+// the same for an offset into the tile viewed as doubles (re, im pairs)
+__device__ __forceinline__ int tpad_d(int slot) { return (tpad(slot >> 1) << 1) | (slot & 1); }
 #ifndef PD_U
 #define PD_U 2  // gather/scatter units in flight per thread
 #endif
@@ -99,7 +107,7 @@ __device__ __forceinline__ void stockham_bfly(cplx (&v)[R], int j, int twsh, int
 // One radix-R pass over 2^lcount sequences of length 2^lL in LDS, in place,
 // spread over the whole workgroup: every thread loads its butterfly inputs,
 // the workgroup synchronises, then the outputs are written.  Element (s, i)
-// is at buf[(s << lss) + (i << lis)].
+// is at buf[tpad((s << lss) + (i << lis))].
 template <int R, int LR>
 __device__ __forceinline__ void stockham_pass(cplx* buf, int lL, int lLs, int lcount, int lis, int lss, int sign,
                                               const Twiddle& tw, int log2M) {
@@ -122,7 +130,7 @@ __device__ __forceinline__ void stockham_pass(cplx* buf, int lL, int lLs, int lc
       }
       const int base = (s << lss) + (b << lis);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = buf[base + ((r << lnb) << lis)];
+      for (int r = 0; r < R; ++r) v[k][r] = buf[tpad(base + ((r << lnb) << lis))];
     }
   }
   __syncthreads();
@@ -142,14 +150,14 @@ __device__ __forceinline__ void stockham_pass(cplx* buf, int lL, int lLs, int lc
       stockham_bfly<R>(v[k], j, twsh, sign, tw);
       const int ob = (s << lss) + ((((b >> lLs) << (lLs + LR)) + j) << lis);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[ob + ((r << lLs) << lis)] = v[k][r];
+      for (int r = 0; r < R; ++r) buf[tpad(ob + ((r << lLs) << lis))] = v[k][r];
     }
   }
   __syncthreads();
 }
 
 // Unnormalised DFT (sign -1) or inverse DFT (sign +1) of 2^lcount sequences
-// of length 2^lL held in LDS (element (s, i) at buf[(s << lss) + (i << lis)],
+// of length 2^lL held in LDS (element (s, i) at buf[tpad((s << lss) + (i << lis))],
 // 2^(lcount + lL) <= 4096).  Caller synchronises before; the result is visible
 // to the whole workgroup on return.  Radix 8 while at least three factors of
 // two remain, then 4 or 2: the fewest passes (each pass costs two workgroup
@@ -278,7 +286,7 @@ struct OpPdct {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int u = base + threadIdx.x + k * MF_THREADS;
-        if (u < units) td[slot[k]] = sgn(idx[k], f.gather(idx[k], in[k]));
+        if (u < units) td[tpad_d(slot[k])] = sgn(idx[k], f.gather(idx[k], in[k]));
       }
     }
     __syncthreads();
@@ -291,7 +299,7 @@ struct OpPdct {
     for (int e = threadIdx.x; e < (N1 << lcb); e += MF_THREADS) {
       const int k1 = e >> lcb, c = e & ((1 << lcb) - 1);
       const int j2 = col_j2(q, c);
-      cplx v = tile[e];
+      cplx v = tile[tpad(e)];
       v = cmul(v, tw.get((j2 * k1) << 3, -1));
       Y1[(q << (l1 + lcb)) + e] = v;
     }
@@ -318,7 +326,7 @@ struct OpPdct {
         f.load(idx[k], in[k]);
       }
     }
-    for (int e = threadIdx.x; e < (N1 << lcb); e += MF_THREADS) tile[e] = Y2[(q << (l1 + lcb)) + e];
+    for (int e = threadIdx.x; e < (N1 << lcb); e += MF_THREADS) tile[tpad(e)] = Y2[(q << (l1 + lcb)) + e];
     __syncthreads();
     lds_fft(tile, l1, lcb, lcb, 0, +1, tw, log2M());
     double* td = reinterpret_cast<double*>(tile);
@@ -337,8 +345,8 @@ struct OpPdct {
       for (int k = 0; k < U; ++k) {
         const int u = base + threadIdx.x + k * MF_THREADS;
         if (u < units) {
-          const double t = sgn(idx[k], td[slot[k]]);
-          if constexpr (F::CHAIN) td[slot[k]] = sgn(idx[k], f.scatter(idx[k], t, in[k]));
+          const double t = sgn(idx[k], td[tpad_d(slot[k])]);
+          if constexpr (F::CHAIN) td[tpad_d(slot[k])] = sgn(idx[k], f.scatter(idx[k], t, in[k]));
           else f.scatter(idx[k], t, in[k]);
         }
       }
@@ -350,7 +358,7 @@ struct OpPdct {
   // Spectral work for one pair of half-spectrum indices (kA, kB = H - kA).
   // acc[0] += sum of squared outputs, acc[1] += sum b~ * output.
   __device__ __forceinline__ void spectral_pair(int mode, int kA, int pA, int kB, int pB, double (&acc)[2]) {
-    const cplx WA = tile[pA];
+    const cplx WA = tile[tpad(pA)];
     const double h = 0.70710678118654752440;
     if (kA == 0) {
       // V_0 = Re W0 + Im W0, V_H = Re W0 - Im W0 (both real)
@@ -373,10 +381,10 @@ struct OpPdct {
       acc[0] += Y0 * Y0 + YH * YH;
       const double c0 = a0 * Y0, cH = a1 * YH;
       const double H0 = c0, HH = cH * h;
-      tile[pA] = mkc(H0 + HH, H0 - HH);  // (H0 + HH) + i (H0 - HH)
+      tile[tpad(pA)] = mkc(H0 + HH, H0 - HH);  // (H0 + HH) + i (H0 - HH)
       return;
     }
-    const cplx WB = tile[pB];
+    const cplx WB = tile[tpad(pB)];
     // real-FFT split: E = (WA + conj WB)/2, O = (WA - conj WB) / (2i)
     const cplx E = cscale(cadd(WA, cconj(WB)), 0.5);
     const cplx Dd = csub(WA, cconj(WB));
@@ -427,11 +435,11 @@ struct OpPdct {
     const cplx HB = cscale(cmul(cconj(tw.get(kB)), mkc(a1 * yb0, -a1 * yb1)), 0.5);
     // G_k = (H_k + conj H_{H-k}) + i exp(2 pi i k/n) (H_k - conj H_{H-k})
     const cplx GA = cadd(cadd(HA, cconj(HB)), cmul_si(cmul(cconj(tw.get(4 * kA)), csub(HA, cconj(HB))), 1));
-    tile[pA] = GA;
+    tile[tpad(pA)] = GA;
     if (!self) {
       const cplx GB =
           cadd(cadd(HB, cconj(HA)), cmul_si(cmul(cconj(tw.get(4 * kB)), csub(HB, cconj(HA))), 1));
-      tile[pB] = GB;
+      tile[tpad(pB)] = GB;
     }
   }
 
@@ -483,7 +491,7 @@ struct OpPdct {
             if (comb) v = mkc(v.x + beta * vb[e].x, v.y + beta * vb[e].y);
             if (mode_in == PB_RESID_STEP || (!lin && mode == PB_RESID)) Yx[gi] = v;
             else if (!lin && mode == PB_HAPPLY) Y1p[gi] = v;
-            tile[s * N2 + col_j2(q, c)] = v;
+            tile[tpad(s * N2 + col_j2(q, c))] = v;
           }
         }
       }
@@ -518,7 +526,7 @@ struct OpPdct {
       const int q = u >> lcb, c = u & ((1 << lcb) - 1);
       const int j2 = col_j2(q, c);
       const int k1 = s ? k1b : k1a;
-      cplx v = tile[s * N2 + j2];
+      cplx v = tile[tpad(s * N2 + j2)];
       v = cmul(v, tw.get((j2 * k1) << 3, +1));
       Y2[(((q << l1) + k1) << lcb) + c] = v;
     }
