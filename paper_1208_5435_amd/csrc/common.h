@@ -26,6 +26,30 @@ struct cplx {
   double x, y;
 };
 
+// A store of an 8- or 16-byte element that writes through the XCD's L2 to
+// memory (device scope, cache policy sc1), for data that workgroups on other
+// XCDs read after the next team barrier: lines written this way are not dirty
+// in the L2 when the barrier's release writes the L2 back, which keeps that
+// write-back short.  base must be the same for the whole wave (it forms a
+// buffer descriptor); idx * sizeof(T) < 2^31.
+typedef int mf_v4i __attribute__((ext_vector_type(4)));
+typedef int mf_v2i __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ void st_wt(T* base, long idx, const T& v) {
+  static_assert(sizeof(T) == 16 || sizeof(T) == 8, "8- or 16-byte elements");
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(base, 0, 0x7fffffff, 0x00020000);
+  if constexpr (sizeof(T) == 16)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(mf_v4i, v), r, (int)(idx * 16), 0, 16 /* sc1 */);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(mf_v2i, v), r, (int)(idx * 8), 0, 16 /* sc1 */);
+}
+// The same or a plain store, as wt says (uniform over the wave).
+template <class T>
+__device__ __forceinline__ void st_sel(T* base, long idx, const T& v, int wt) {
+  if (wt) st_wt(base, idx, v);
+  else base[idx] = v;
+}
+
 __device__ __forceinline__ cplx mkc(double a, double b) { return cplx{a, b}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.x - b.x, a.y - b.y}; }
@@ -267,10 +291,12 @@ __device__ __forceinline__ void wg_reduce(const int* kinds, double (&v)[K], doub
 
 // Reduce per-item partials part[item * MF_MAXK + j] over items [0, nitems) in
 // a fixed order; every thread of the workgroup receives the K results.  Lane
-// l folds items l, l + 64, l + 128, ... in that order; the loads of four such
-// items are issued together before they are folded, so that a team of a few
-// hundred workgroups pays one memory round trip here instead of one per item.
-template <int K>
+// l folds items l, l + 64, l + 128, ... in that order; the loads of RU such
+// items are issued together before they are folded.  RU = 4 lets a team of a
+// few hundred workgroups pay one memory round trip here instead of one per
+// item, at the price of 4 K more live registers in the calling code (the
+// operators whose teams are that large take it; the others keep RU = 1).
+template <int K, int RU = 1>
 __device__ __forceinline__ void reduce_items(const int* kinds, const double* part, int nitems, double (&res)[K],
                                     double* lds_scratch) {
   if (threadIdx.x < 64) {
@@ -278,7 +304,6 @@ __device__ __forceinline__ void reduce_items(const int* kinds, const double* par
     double a[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) a[j] = rid(kinds[j]);
-    constexpr int RU = 4;
     for (int it0 = lane; it0 < nitems; it0 += 64 * RU) {
       double v[RU][K];
 #pragma unroll

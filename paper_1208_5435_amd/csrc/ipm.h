@@ -170,6 +170,7 @@ struct FPcgC2 {
   double2* R;
   double alpha, beta, rho;
   int first;
+  int wt;  // stores write through the L2 (teams of several workgroups)
   double acc[K];
   __device__ void reset() {
 #pragma unroll
@@ -190,9 +191,9 @@ struct FPcgC2 {
     const double qu = in.ti.x * p.x + t, qv = in.ti.y * p.y - t;
     const double2 x = make_double2(in.x.x + alpha * p.x, in.x.y + alpha * p.y);
     const double2 r = make_double2(in.r.x - alpha * qu, in.r.y - alpha * qv);
-    X[i] = x;
-    R[i] = r;
-    P[i] = p;
+    st_sel(X, i, x, wt);
+    st_sel(R, i, r, wt);
+    st_sel(P, i, p, wt);
     double zu, zv;
     precond_apply(in.ti.x, in.ti.y, rho, r.x, r.y, zu, zv);
     acc[0] += r.x * zu + r.y * zv;
@@ -660,6 +661,19 @@ __device__ __forceinline__ void run_B<OpDenseDirect>(Ctx& cx, OpDenseDirect& op,
   run_B<OpDense>(cx, op, mode, part, out, beta, first);
 }
 
+// loads in flight per lane in the reductions over items (see reduce_items)
+template <class OP>
+__device__ constexpr int red_unroll() {
+  return (std::is_same<OP, OpPdct>::value || std::is_same<OP, OpWht>::value) ? 4 : 1;
+}
+
+// whether the PCG vector stores write through the L2 (see st_wt)
+__device__ __forceinline__ int op_write_through(const OpPdct& op) { return op.wt; }
+template <class OP>
+__device__ __forceinline__ int op_write_through(const OP&) {
+  return 0;
+}
+
 // the search-direction buffers of iteration `it` (dense: alternating d of p)
 __device__ __forceinline__ void op_direction(OpDense& op, const TeamWS& w, int it) {
   op.Dp_prev = (it & 1) ? w.Dp0 : w.Dp1;
@@ -842,6 +856,10 @@ __device__ __forceinline__ void make_op(OpPdct& op, const KArgs& a, const InstDe
   op.cur_k1a = 0;
   op.tw.scale_shift = a.tw_log2n_max - op.logn;
   op.tile = (cplx*)lds;
+  // Write-through pays at large lengths only (measured: it shortens the
+  // barriers' L2 write-back at n = 2^18 and 2^20, and costs more than it
+  // saves at n = 2^16 and for one-workgroup teams, which skip that write-back).
+  op.wt = team_size > 1 && d.n >= (1L << 18);
   op.a0 = sqrt(1.0 / (double)d.n);
   op.a1 = sqrt(2.0 / (double)d.n);
   op.flip = a.op_flip;
@@ -997,7 +1015,7 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
       break;
     }
     double pB[1];
-    reduce_items<1>(kB, w.partB, op.nB(), pB, cx.red);
+    reduce_items<1, red_unroll<OP>()>(kB, w.partB, op.nB(), pB, cx.red);
     ++it;
     const double pq = ptp + pB[0];
     if (!(pq > 0.0)) {
@@ -1022,6 +1040,7 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
       fc.alpha = gamma / pq;
       fc.beta = beta;
       fc.first = first;
+      fc.wt = op_write_through(op);
       run_C(cx, op, fc, kC, w.partC);
     }
     if (team_barrier(cx.t)) {
@@ -1029,7 +1048,7 @@ __device__ __forceinline__ int pcg_run(Ctx& cx, OP& op, const TeamWS& w, double 
       break;
     }
     double pC[5];
-    reduce_items<5>(kC, w.partC, op.nC(), pC, cx.red);
+    reduce_items<5, red_unroll<OP>()>(kC, w.partC, op.nC(), pC, cx.red);
     beta = pC[0] / gamma;
     gamma = pC[0];
     rr = pC[1];
@@ -1073,13 +1092,13 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
       o.status = ST_ABORTED;
       return o;
     }
-    reduce_items<2>(kA, w.partA, op.nA(), pA, cx.red);
+    reduce_items<2, red_unroll<OP>()>(kA, w.partA, op.nA(), pA, cx.red);
     run_B<OP>(cx, op, 1, w.partB, nullptr);
     if (team_barrier(cx.t)) {
       o.status = ST_ABORTED;
       return o;
     }
-    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
+    reduce_items<2, red_unroll<OP>()>(kb, w.partB, op.nB(), pB, cx.red);
     op_x_advance(op);
   } else {
     // The step pass left the transform of the step direction; the operator's
@@ -1094,8 +1113,8 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
       o.status = ST_ABORTED;
       return o;
     }
-    reduce_items<2>(kb, w.partB, op.nB(), pB, cx.red);
-    reduce_items<2>(kA, w.partS, (int)((op.n + (1L << lchunk) - 1) >> lchunk), pA, cx.red);
+    reduce_items<2, red_unroll<OP>()>(kb, w.partB, op.nB(), pB, cx.red);
+    reduce_items<2, red_unroll<OP>()>(kA, w.partS, (int)((op.n + (1L << lchunk) - 1) >> lchunk), pA, cx.red);
     if (mode == RA_STEP) op_x_advance(op);
   }
   o.sumz = pA[0];
@@ -1125,7 +1144,7 @@ __device__ __forceinline__ ResOut residual_rhs(Ctx& cx, OP& op, const TeamWS& w,
     return o;
   }
   double pC[4];
-  reduce_items<4>(kC, w.partC, op.nC(), pC, cx.red);
+  reduce_items<4, red_unroll<OP>()>(kC, w.partC, op.nC(), pC, cx.red);
   o.ginf = pC[0];
   o.rhs2 = pC[1];
   o.rty = pC[2];
@@ -1229,7 +1248,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
         break;
       }
       double rs[2];
-      reduce_items<2>(kS, w.partA, op.nA(), rs, cx.red);
+      reduce_items<2, red_unroll<OP>()>(kS, w.partA, op.nA(), rs, cx.red);
       aP = fmin(1.0, prm.eta * rs[0]);
       aD = fmin(1.0, prm.eta * rs[1]);
       if (aP <= prm.alpha_tilde || aD <= prm.alpha_tilde) {
@@ -1260,7 +1279,7 @@ __device__ __forceinline__ void solve_instance(Ctx& cx, const KArgs& a, int ii, 
           status = ST_ABORTED;
           break;
         }
-        reduce_items<2>(kS, w.partA, op.nA(), rs, cx.red);
+        reduce_items<2, red_unroll<OP>()>(kS, w.partA, op.nA(), rs, cx.red);
         aP = fmin(1.0, prm.eta * rs[0]);
         aD = fmin(1.0, prm.eta * rs[1]);
         ++ncorr;
@@ -1358,7 +1377,7 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
     run_A(cx, op, fi, kI, w.partA);
     if (team_barrier(cx.t)) st = ST_ABORTED;
     double pI[3];
-    reduce_items<3>(kI, w.partA, op.nA(), pI, cx.red);
+    reduce_items<3, red_unroll<OP>()>(kI, w.partA, op.nA(), pI, cx.red);
     if (!st)
       st = pcg_run<OP, RED>(cx, op, w, rho, prm.tolpcg_adj, prm.mxiterpcg_adj, pI[1], pI[0], pI[2], &its, &capped);
     status = st;
@@ -1372,7 +1391,7 @@ __device__ __forceinline__ void backward_instance(Ctx& cx, const KArgs& a, int i
       run_A(cx, op, fg, kG, w.partA);
       if (team_barrier(cx.t)) status = ST_ABORTED;
       double pG[1];
-      reduce_items<1>(kG, w.partA, op.nA(), pG, cx.red);
+      reduce_items<1, red_unroll<OP>()>(kG, w.partA, op.nA(), pG, cx.red);
       gtau = -pG[0];
       if (!status) {
         op_forward_out(cx, op, w, a.grad_b + d.m_off);

@@ -206,6 +206,7 @@ struct OpPdct {
   cplx* tile;          // LDS
   unsigned char* msk;  // LDS: mask of the current pass-B item, rows (k1a, k1b)
   int cur_k1a;
+  int wt;  // exchange buffers are written through the L2 (teams of several workgroups)
   double a0, a1;
   // Partial DST-II through the same transform: S d = P C D d with D =
   // diag((-1)^j) and P the index reversal k -> n - 1 - k (the sine rows are
@@ -301,7 +302,7 @@ struct OpPdct {
       const int j2 = col_j2(q, c);
       cplx v = tile[tpad(e)];
       v = cmul(v, tw.get((j2 * k1) << 3, -1));
-      Y1[(q << (l1 + lcb)) + e] = v;
+      st_sel(Y1, (q << (l1 + lcb)) + e, v, wt);
     }
     __syncthreads();
   }
@@ -489,8 +490,8 @@ struct OpPdct {
             const int gi = (((q << l1) + (s ? k1b : k1a)) << lcb) + c;
             cplx v = va[e];
             if (comb) v = mkc(v.x + beta * vb[e].x, v.y + beta * vb[e].y);
-            if (mode_in == PB_RESID_STEP || (!lin && mode == PB_RESID)) Yx[gi] = v;
-            else if (!lin && mode == PB_HAPPLY) Y1p[gi] = v;
+            if (mode_in == PB_RESID_STEP || (!lin && mode == PB_RESID)) st_sel(Yx, gi, v, wt);
+            else if (!lin && mode == PB_HAPPLY) st_sel(Y1p, gi, v, wt);
             tile[tpad(s * N2 + col_j2(q, c))] = v;
           }
         }
@@ -528,7 +529,7 @@ struct OpPdct {
       const int k1 = s ? k1b : k1a;
       cplx v = tile[tpad(s * N2 + j2)];
       v = cmul(v, tw.get((j2 * k1) << 3, +1));
-      Y2[(((q << l1) + k1) << lcb) + c] = v;
+      st_sel(Y2, (((q << l1) + k1) << lcb) + c, v, wt);
     }
     __syncthreads();
   }
