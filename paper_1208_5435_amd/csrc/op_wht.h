@@ -33,7 +33,16 @@ __device__ __forceinline__ void lds_wht(double* buf, int lL, int lcount, int lis
     if (lL - lh >= 2) {
       const int lq = lL - 2;  // log2 quads per sequence
       for (int t = threadIdx.x; t < (total >> 2); t += MF_THREADS) {
-        const int s = t >> lq, j = t & ((1 << lq) - 1);
+        int s, j;
+        if (lis == 0) {
+          s = t >> lq;
+          j = t & ((1 << lq) - 1);
+        } else {
+          // interleaved sequences: neighbouring lanes take neighbouring
+          // sequences (adjacent LDS words) rather than quads 2^(lis+2) apart
+          s = t & ((1 << lcount) - 1);
+          j = t >> lcount;
+        }
         const int i0 = ((j >> lh) << (lh + 2)) | (j & ((1 << lh) - 1));
         const int h = 1 << lh;
         double* p0 = buf + (s << lss);
@@ -49,7 +58,14 @@ __device__ __forceinline__ void lds_wht(double* buf, int lL, int lcount, int lis
     } else {
       const int lp = lL - 1;  // log2 pairs per sequence
       for (int t = threadIdx.x; t < (total >> 1); t += MF_THREADS) {
-        const int s = t >> lp, j = t & ((1 << lp) - 1);
+        int s, j;
+        if (lis == 0) {
+          s = t >> lp;
+          j = t & ((1 << lp) - 1);
+        } else {
+          s = t & ((1 << lcount) - 1);
+          j = t >> lcount;
+        }
         const int i0 = ((j >> lh) << (lh + 1)) | (j & ((1 << lh) - 1));
         double* p0 = buf + (s << lss);
         const int o0 = i0 << lis, o1 = (i0 + (1 << lh)) << lis;
