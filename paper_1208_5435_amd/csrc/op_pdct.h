@@ -41,7 +41,7 @@ __device__ __forceinline__ int tpad(int a) { return a + (a >> PD_PAD_SH); }
 // the same for an offset into the tile viewed as doubles (re, im pairs)
 __device__ __forceinline__ int tpad_d(int slot) { return (tpad(slot >> 1) << 1) | (slot & 1); }
 #ifndef PD_U
-#define PD_U 2  // gather/scatter units in flight per thread
+#define PD_U 1  // gather/scatter units per thread and batch (2 or more raise the kernel's register spills; measured slower)
 #endif
 #define PD_MASK_BYTES 8192  // LDS staging of one pass-B item's mask (4 N2 <= 8192)
 
