@@ -63,27 +63,28 @@ def test_batched_equals_single_bitwise(solver):
         assert r1.infos[0]["ipm_iters"] == res.infos[j]["ipm_iters"]
 
 
-def test_write_through_team_equals_one_workgroup(solver):
-    """n = 2^18: a team of 64 workgroups stores the exchange buffers and the
-    PCG vectors through the L2 (the write-through path of multi-workgroup
-    teams at n >= 2^18) and synchronises over the XCDs; a team of one
-    workgroup does neither.  Both cut the work into the same items, so the
-    fixed-order reductions give bit-identical results."""
-    n = 1 << 18
-    inst = W.dct_instance(n, n // 4, n // 100, seed=4242, sigma=1e-2, c_tau=5e-3)
+@pytest.mark.parametrize("logn,team", [(18, 64), (20, 128)])
+def test_write_through_team_equals_one_workgroup(solver, logn, team):
+    """A team of several workgroups stores the exchange buffers and the PCG
+    vectors through the L2 (the write-through path of multi-workgroup teams at
+    n >= 2^18) and synchronises over the XCDs; a team of one workgroup does
+    neither.  At these team sizes both cut the work into the same items, so
+    the fixed-order reductions give bit-identical results."""
+    n = 1 << logn
+    inst = W.dct_instance(n, n // 4, n // 100, seed=4242 + logn, sigma=1e-2, c_tau=5e-3)
     out = {}
     try:
-        for wg in (1, 64):
-            say(f"write-through check: n=2^18, {wg} workgroup(s)")
+        for wg in (1, team):
+            say(f"write-through check: n=2^{logn}, {wg} workgroup(s)")
             solver.set_launch(wg, 0, 0)
             r = solver.solve(inst.b, inst.tau, rows=inst.rows, n=n)
             out[wg] = (r.x.cpu().numpy(), r.infos[0])
     finally:
         solver.set_launch(0, 0, 0)
-    (x1, i1), (x64, i64) = out[1], out[64]
-    assert i1["status"] == i64["status"] == 0, (i1, i64)
-    assert (i1["ipm_iters"], i1["pcg_iters"]) == (i64["ipm_iters"], i64["pcg_iters"])
-    assert np.array_equal(x1, x64)
+    (x1, i1), (xt, it) = out[1], out[team]
+    assert i1["status"] == it["status"] == 0, (i1, it)
+    assert (i1["ipm_iters"], i1["pcg_iters"]) == (it["ipm_iters"], it["pcg_iters"])
+    assert np.array_equal(x1, xt)
 
 
 def test_batched_pdct_uneven_lengths(solver):
